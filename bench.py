@@ -1,0 +1,172 @@
+"""Benchmark: cell-updates/s of the full extended-Boussinesq time step (FP32)
+on one MI355X, on the 4096 x 4096 continental-shelf workload (64 JONSWAP
+components at the west side, 64-cell sponge east, walls north/south,
+fractal bathymetry noise; predictor + 2 correctors per step).
+
+Prints one JSON line.  `value` = cells * steps / wall seconds of the timed
+steps (inputs resident in HBM).  `roofline` reports the dominant kernel:
+algorithmic bytes per launch (the kernel's compulsory reads and writes, see
+ALG_BYTES) divided by its average duration, timed with HIP events recorded on
+the library's launch stream over a second pass of the same steps.
+`cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
+workload (after its two Euler start-up steps, a few full steps).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# Compulsory FP32 words per cell of each kernel class (reads + writes), for
+# the default configuration (linear F* extrapolation, two correctors):
+#   predictor: reads eta, P, Q, corner depth, history n-1 (E, F, G, F*, G*),
+#              history n-2 (E, F, G); writes history n (5), corrector bases (3),
+#              eta, U*, V*                                   -> 12 + 11 = 23
+#   corrector: reads eta, P, Q, depth, bases (3); writes eta, U*, V* -> 7 + 3 = 10
+#   reduce:    reads U*, V*, depth; writes eliminated U*, V*, reduced equations
+#              (4 words per 2 ends of a 64-cell row / 16-cell column segment)
+#                                                            -> 3 + 2 + 0.625
+#   pcr:       reads the reduced equations, writes their solutions -> 0.78
+#   expand:    reads eliminated U*, V*, depth, eta, end values; writes P, Q
+#                                                            -> 4.16 + 2
+ALG_WORDS = {"k_stencil[predictor]": 23.0, "k_stencil[corrector]": 10.0,
+             "k_reduce": 5.625, "k_pcr": 0.78125, "k_expand": 6.15625}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=4096, help="grid side (cells)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    return ap.parse_args()
+
+
+def cpu_baseline(w, steps):
+    import numpy as np
+    import oracle
+    z = w.z.astype(np.float32).astype(np.float64)
+    D = oracle.Domain(w.nx, w.ny, w.dx, w.dy, w.dt, z)
+    for s, side in enumerate(w.sides):
+        if side.kind != 0:
+            D.set_boundary(s, side.kind, side.width, side.amp, side.period, side.theta,
+                           side.phase or None)
+    D.advance(2)                      # Euler start-up steps (one pass each), untimed
+    t = time.perf_counter()
+    D.advance(steps)
+    dt = time.perf_counter() - t
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": w.nx * w.ny * steps / dt, "unit": "cell-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "%s, %d full steps (predictor + 2 correctors) after the 2 Euler "
+                      "start-up steps, FP64, %.1f s" % (w.name, steps, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU; --gpus %d is not supported "
+              "(the multi-GPU decomposition is design-only)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1611_05984_amd import wavestep as ws
+    from paper_1611_05984_amd import workloads as wl
+
+    torch.cuda.set_device(0)
+    w = wl.config3(n=args.n)
+    D = ws.Domain(w.nx, w.ny, w.dx, w.dy, w.dt, w.z, device="cuda:0")
+    for s, side in enumerate(w.sides):
+        if side.kind != 0:
+            D.set_boundary(s, side.kind, side.width, side.amp, side.period, side.theta,
+                           side.phase or None)
+    print("bench: %s ready, warmup %d steps" % (w.name, args.warmup), file=sys.stderr, flush=True)
+    D.advance(args.warmup)
+    torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    D.advance(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step, tsim, health = D.query()
+    if health:
+        print("bench: non-finite state", file=sys.stderr)
+        sys.exit(1)
+    cells = w.nx * w.ny
+    value = cells * args.steps / wall
+    print("bench: timed %d steps in %.3f s" % (args.steps, wall), file=sys.stderr, flush=True)
+
+    # per-kernel durations from HIP events on the launch stream (second pass)
+    D.profile(True)
+    D.advance(args.steps)
+    prof = D.profile_collect()
+    D.profile(False)
+    tot = sum(ms for ms, n in prof.values())
+    dom_name = max(prof, key=lambda k: prof[k][0])
+    dom_ms, dom_n = prof[dom_name]
+    avg_s = dom_ms / dom_n / 1e3
+    alg_bytes = ALG_WORDS[dom_name] * 4.0 * cells
+    achieved = alg_bytes / avg_s / 1e9
+    step_words = (ALG_WORDS["k_stencil[predictor]"] + 2 * ALG_WORDS["k_stencil[corrector]"] +
+                  3 * (ALG_WORDS["k_reduce"] + ALG_WORDS["k_pcr"] + ALG_WORDS["k_expand"]))
+    kernels = {k: {"ms_avg": (ms / n if n else 0.0), "launches": n,
+                   "share": (ms / tot if tot else 0.0),
+                   "alg_GBs": (ALG_WORDS[k] * 4 * cells / (ms / n / 1e3) / 1e9 if n else 0.0)}
+               for k, (ms, n) in prof.items()}
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tpath):
+        tr = json.load(open(tpath))
+        if tr.get("kernel") == dom_name and tr.get("source_hash") == _source_hash():
+            traffic = tr.get("bytes_per_launch")
+
+    out = {
+        "metric": "cell-updates/s per full step (FP32)",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded shelf bathymetry + fractal noise, JONSWAP maker)",
+        "config": {"workload": w.name + "_jonswap64_sponge64", "nx": w.nx, "ny": w.ny,
+                   "dx_m": w.dx, "dt_s": w.dt, "n_corr": 2, "fstar_extrap": 1,
+                   "boundaries": "W waves(64 comps) / E sponge(64) / N,S walls"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": dom_name, "kernel_ms_avg": dom_ms / dom_n,
+                     "alg_bytes_per_launch": alg_bytes},
+        "step_hbm": {"alg_bytes_per_cell_step": step_words * 4,
+                     "alg_GBs": value * step_words * 4 / 1e9,
+                     "frac_of_peak": value * step_words * 4 / 1e9 / HBM_PEAK_GBS},
+        "kernels": kernels,
+        "sim": {"step": step, "t_s": tsim},
+    }
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+def _source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("ws_device.hpp", "ws_kernels.hpp", "wavestep.hip"):
+        h.update(open(os.path.join(ROOT, "paper_1611_05984_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    main()

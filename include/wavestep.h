@@ -1,0 +1,185 @@
+/*
+ * wavestep.h -- C ABI of the MI355X (gfx950) time step of the hybrid
+ * finite-volume / finite-difference extended-Boussinesq solver of
+ * Tavakkol & Lynett, "Celeris" (arXiv:1611.05984).
+ *
+ * One time step (sec. 2.3) = a predictor pass (third-order Adams-Bashforth,
+ * eqs. 15-17) and n_corr corrector passes (fourth-order Adams-Moulton,
+ * eqs. 18-20).  Each pass evaluates the right-hand side (KP07 central-upwind
+ * fluxes with generalized-minmod reconstruction, positivity correction and
+ * desingularized velocities, sec. 2.2 steps 1-4 and eq. 14; central
+ * finite-difference dispersive terms of eqs. 10-13; friction eqs. 31-32),
+ * integrates w, U*, V*, and recovers P and Q from the row and column
+ * tridiagonal systems of eqs. 21-23.  Boundaries: solid walls (sec. 2.4.1),
+ * sine/irregular wave makers (sec. 2.4.2, eqs. 25-29), sponge layers
+ * (sec. 2.4.3, eq. 30).  Solitary waves: sec. 2.7, eqs. 33-36.
+ *
+ * Conventions
+ *  - Every length is in metres, every time in seconds, g in m/s^2.
+ *  - Cells (i, j), i in [0, nx), j in [0, ny), centre ((i+1/2)dx, (j+1/2)dy).
+ *    2-D arrays are row-major with x fastest; "pitch" is the row stride in
+ *    elements (>= nx).
+ *  - Bathymetry is the bottom elevation z at the cell corners (i dx, j dy),
+ *    (ny+1) rows of (nx+1) values, above the same datum as the water surface
+ *    w; the bottom is continuous and bilinear between corners.
+ *  - Device pointers are HIP device addresses; "stream" is a hipStream_t
+ *    (NULL = the null stream).  Calls that take a stream are asynchronous
+ *    unless stated otherwise.
+ *  - Ownership: the caller allocates the workspace (ws_workspace_bytes()) and
+ *    every array it passes; the library borrows the workspace until
+ *    ws_domain_destroy() and never frees caller memory.  Host arrays are read
+ *    only during the call.  Handles are library-owned; one handle must not be
+ *    used from two threads at once.
+ *  - Errors: every call returns a ws_status; nothing aborts or throws across
+ *    the ABI.  ws_last_error() returns a thread-local description of the last
+ *    failure.  Faults found by kernels (non-finite state) set a per-domain
+ *    health word that the next synchronous call (ws_query) reports.
+ */
+#ifndef WAVESTEP_H
+#define WAVESTEP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ws_domain ws_domain; /* opaque, library-owned */
+typedef struct ws_batch ws_batch;   /* opaque, library-owned */
+
+typedef enum {
+    WS_OK = 0,
+    WS_EINVAL = -1,      /* bad argument                                        */
+    WS_ENOMEM = -2,      /* workspace too small / host allocation failed        */
+    WS_EHIP = -3,        /* a HIP runtime call failed                           */
+    WS_ENOTDD = -4,      /* a row/column system of eq. 23 is not diagonally dominant */
+    WS_ENONFINITE = -5,  /* the state became non-finite                         */
+    WS_EBUSY = -6        /* batch full / slot in use                            */
+} ws_status;
+
+enum { WS_BSNQ = 0, WS_NLSW = 1 };                               /* model (sec. 3.2)  */
+enum { WS_FRIC_NONE = 0, WS_FRIC_QUAD = 1, WS_FRIC_MANNING = 2 }; /* eqs. 31, 32       */
+enum { WS_WEST = 0, WS_EAST = 1, WS_SOUTH = 2, WS_NORTH = 3 };
+enum { WS_BC_SOLID = 0, WS_BC_SPONGE = 1, WS_BC_WAVES = 2 };     /* sec. 2.4          */
+enum { WS_EDIT_ADD_WATER = 0, WS_EDIT_RAISE_TERRAIN = 1 };       /* sec. 1 edits      */
+enum { WS_READ_W = 0, WS_READ_H = 1 };                           /* first field of ws_read */
+
+/* Grid and model parameters.  Defaults in brackets follow the paper: B = 1/15
+ * (sec. 2.1), eps = 5e-12 and two correctors (Fig. 2), g = 9.81, theta = 1.3
+ * (generalized minmod, sec. 2.2 step 1; the paper gives no value).
+ * fstar_extrap selects the predictor's extrapolation of F*, G*: 2 = the
+ * quadratic form printed in eqs. 16-17, 1 = linear (default; the printed form
+ * is linearly unstable in 2-D with two correctors once d/dx > ~4.5), 0 = none.
+ * The first two steps after ws_domain_init / ws_set_state are first-order
+ * Euler steps without correctors (sec. 2.3). */
+typedef struct {
+    int32_t nx, ny;          /* cells, >= 2 each                                  */
+    int32_t n_corr;          /* corrector passes per step [2]                     */
+    int32_t model;           /* WS_BSNQ or WS_NLSW [WS_BSNQ]                      */
+    int32_t friction;        /* WS_FRIC_* [WS_FRIC_NONE]                          */
+    int32_t fstar_extrap;    /* 0, 1 or 2 [1]                                     */
+    double dx, dy, dt;       /* spacing and fixed time step, > 0                  */
+    double g;                /* [9.81]                                            */
+    double still_water;      /* still water surface elevation w_s [0]             */
+    double Bcoef;            /* dispersion coefficient B [1/15]                   */
+    double theta;            /* minmod parameter in [1, 2] [1.3]                  */
+    double eps;              /* desingularization tolerance of eq. 14 [5e-12]     */
+    double friction_coef;    /* f of eq. 31 or Manning n of eq. 32 [0]            */
+} ws_grid;
+
+/* One side's boundary condition.  WS_BC_WAVES superposes n_comp sine
+ * components (eqs. 25-28; wave number from Eckart's eq. 29 at ref_depth, or,
+ * when ref_depth <= 0, at the mean still water depth of the first interior
+ * row/column along that side).  WS_BC_SPONGE is a wall whose width_cells
+ * nearest cells are damped once per step by eq. 30.  Host arrays, length
+ * n_comp (<= 256), read during the call; phase may be NULL (zeros). */
+typedef struct {
+    int32_t type;            /* WS_BC_*                                           */
+    int32_t width_cells;     /* sponge width in cells                             */
+    int32_t n_comp;          /* wave components                                   */
+    int32_t reserved;
+    const double *amp;       /* amplitude a, m                                    */
+    const double *period;    /* period T, s                                       */
+    const double *theta_rad; /* direction from +x, radians                        */
+    const double *phase;     /* phase offset, radians                             */
+    double ref_depth;        /* m; <= 0: mean depth along the side                */
+} ws_boundary;
+
+/* Fill *g with the defaults above for an nx x ny grid (dx, dy, dt left 0). */
+void ws_grid_defaults(ws_grid *g, int32_t nx, int32_t ny);
+
+/* Device bytes the caller must supply to ws_domain_init for this grid
+ * (0 if the grid is invalid). */
+size_t ws_workspace_bytes(const ws_grid *g);
+
+/* Create a domain in the caller's device workspace.  z_corners_dev: device
+ * array of (ny+1)*(nx+1) floats, bathymetry at the cell corners (copied; the
+ * caller may free it after the call returns).  All sides start as solid walls
+ * and the state as a lake at rest (w = max(w_s, cell bottom), P = Q = 0).
+ * Synchronous.  Returns WS_ENOTDD if a system of eq. 23 is not diagonally
+ * dominant (bed too steep for the grid). */
+ws_status ws_domain_init(const ws_grid *g, const float *z_corners_dev, void *workspace_dev,
+                         size_t workspace_bytes, void *stream, ws_domain **out);
+
+ws_status ws_domain_destroy(ws_domain *d);
+
+/* Boundary condition of one side (WS_WEST..WS_NORTH).  Synchronous. */
+ws_status ws_set_boundary(ws_domain *d, int32_t side, const ws_boundary *b);
+
+/* Hot start (sec. 3.2): device arrays w (surface elevation), P, Q with row
+ * pitch `pitch` elements; t is the time of this state.  Restarts the
+ * multistep history (the next two steps are Euler steps). */
+ws_status ws_set_state(ws_domain *d, const float *w, const float *P, const float *Q,
+                       int32_t pitch, double t, void *stream);
+
+/* Superpose a solitary wave of height H (sign allowed), direction theta
+ * (radians), crest through (x0, y0), eqs. 33-36, where the still water depth
+ * is positive.  The depth of eqs. 35-36 is the still water depth of the
+ * bilinear bottom at (x0, y0); WS_EINVAL if that is not positive. */
+ws_status ws_add_solitary(ws_domain *d, double H, double theta, double x0, double y0,
+                          void *stream);
+
+/* Advance nsteps full time steps (predictor + n_corr correctors each).
+ * Asynchronous on `stream`. */
+ws_status ws_advance(ws_domain *d, int64_t nsteps, void *stream);
+
+/* Copy the state to device arrays (row pitch `pitch`): first field w
+ * (what = WS_READ_W) or depth h = w - cell bottom (WS_READ_H), then P, Q.
+ * Any pointer may be NULL.  Asynchronous. */
+ws_status ws_read(ws_domain *d, int32_t what, float *first, float *P, float *Q, int32_t pitch,
+                  void *stream);
+
+/* Interactive edit (sec. 1): add a Gaussian hump amp*exp(-r^2/(2 sigma^2))
+ * centred at (x0, y0) to the water surface (WS_EDIT_ADD_WATER) or to the
+ * terrain corners (WS_EDIT_RAISE_TERRAIN; amp < 0 lowers it).  The surface
+ * is then kept at or above the bottom and P, Q are desingularized where the
+ * water is thinner than eps^(1/4).  A terrain edit that would make a system
+ * of eq. 23 lose diagonal dominance is rejected with WS_ENOTDD and changes
+ * nothing.  Synchronous for terrain edits, asynchronous for water edits. */
+ws_status ws_apply_edit(ws_domain *d, int32_t kind, double x0, double y0, double amp,
+                        double sigma, void *stream);
+
+/* Synchronize `stream` and report the number of completed steps, the
+ * simulated time and the health word (0 = finite state).  Returns
+ * WS_ENONFINITE when the health word is set. */
+ws_status ws_query(ws_domain *d, void *stream, int64_t *step, double *t, int32_t *health);
+
+/* Kernel timing for measurement.  While enabled, ws_advance brackets every
+ * kernel launch with HIP events recorded on the launch stream.
+ * ws_profile_collect synchronizes `stream`, adds each kernel class's summed
+ * duration (ms) and launch count into total_ms[k] / launches[k] for
+ * k < n (classes WS_K_*), and clears the recorded events. */
+enum { WS_K_PREDICTOR = 0, WS_K_CORRECTOR = 1, WS_K_REDUCE = 2, WS_K_PCR = 3, WS_K_EXPAND = 4,
+       WS_K_COUNT = 5 };
+ws_status ws_profile_enable(ws_domain *d, int32_t on);
+ws_status ws_profile_collect(ws_domain *d, void *stream, double *total_ms, int64_t *launches,
+                             int32_t n);
+
+/* Thread-local description of the last error. */
+const char *ws_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

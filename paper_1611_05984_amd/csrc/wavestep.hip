@@ -1,0 +1,632 @@
+// wavestep.hip -- host side of the gfx950 time step: workspace layout, the
+// C ABI of include/wavestep.h, and the launch sequence of one step.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/wavestep.h"
+#include "ws_kernels.hpp"
+
+using namespace ws;
+
+// ------------------------------------------------------------ error handling
+static thread_local std::string g_err;
+
+static ws_status fail(ws_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIPCHK(x)                                                                          \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess)                                                              \
+            return fail(WS_EHIP, "%s: %s (%s:%d)", #x, hipGetErrorString(e_), __FILE__, __LINE__); \
+    } while (0)
+
+extern "C" const char *ws_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------------ domain
+struct ws_domain {
+    ws_grid g;
+    int nxp, nyp, pitch, zpitch, nu, nv;
+    char *base;
+    size_t bytes;
+    float *D, *Dnew;               // corner still-water depth (+ scratch for terrain edits)
+    float *st[3][3];               // state of the step and two estimates (eta, P, Q)
+    float *rx, *ry;                // U*, V* increments / eliminated segments
+    float *S[3];                   // corrector bases
+    float *hist[3][5];             // [slot][E, F, G, F*, G*]
+    float4 *redx, *redy;
+    float *solx, *soly;
+    double *tab[4];                // wave tables
+    int *health;
+    double *scal;                  // small device scratch (reductions)
+    int side_type[4], side_width[4], side_ncomp[4];
+    int cur;
+    int64_t step;
+    double t;
+    bool prof_on;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof;  // (class, start, stop)
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+static int roundup(int x, int m) { return (x + m - 1) / m * m; }
+
+struct Layout {
+    int nxp, nyp, pitch, zpitch, nu, nv;
+    size_t field, corners, redx, redy, solx, soly, tabs, misc, total;
+};
+
+static bool grid_ok(const ws_grid *g) {
+    return g && g->nx >= 2 && g->ny >= 2 && g->dx > 0 && g->dy > 0 && g->dt > 0 && g->g > 0 &&
+           g->n_corr >= 0 && g->n_corr <= 64 && (g->model == WS_BSNQ || g->model == WS_NLSW) &&
+           g->friction >= 0 && g->friction <= 2 && g->fstar_extrap >= 0 && g->fstar_extrap <= 2 &&
+           g->theta >= 1.0 && g->theta <= 2.0 && g->eps > 0;
+}
+
+static Layout layout(const ws_grid *g) {
+    Layout L;
+    L.nxp = roundup(g->nx, TX);
+    L.nyp = roundup(g->ny, TY);
+    L.pitch = L.nxp;
+    L.zpitch = roundup(g->nx + 1, 64);
+    L.nu = 2 * (L.nxp / TX);
+    L.nv = 2 * (L.nyp / TY);
+    L.field = align256(sizeof(float) * (size_t)L.nyp * L.pitch);
+    L.corners = align256(sizeof(float) * (size_t)(g->ny + 1) * L.zpitch);
+    L.redx = align256(sizeof(float4) * (size_t)L.nyp * L.nu);
+    L.redy = align256(sizeof(float4) * (size_t)L.nxp * L.nv);
+    L.solx = align256(sizeof(float) * (size_t)L.nyp * L.nu);
+    L.soly = align256(sizeof(float) * (size_t)L.nxp * L.nv);
+    L.tabs = align256(sizeof(double) * MAXC * TABW);
+    L.misc = 256;
+    L.total = 29 * L.field + 2 * L.corners + L.redx + L.redy + L.solx + L.soly + 4 * L.tabs + L.misc;
+    return L;
+}
+
+extern "C" void ws_grid_defaults(ws_grid *g, int32_t nx, int32_t ny) {
+    std::memset(g, 0, sizeof *g);
+    g->nx = nx;
+    g->ny = ny;
+    g->n_corr = 2;
+    g->model = WS_BSNQ;
+    g->friction = WS_FRIC_NONE;
+    g->fstar_extrap = 1;
+    g->g = 9.81;
+    g->still_water = 0.0;
+    g->Bcoef = 1.0 / 15.0;
+    g->theta = 1.3;
+    g->eps = 5e-12;
+    g->friction_coef = 0.0;
+}
+
+extern "C" size_t ws_workspace_bytes(const ws_grid *g) {
+    if (!grid_ok(g)) return 0;
+    return layout(g).total;
+}
+
+static Dom make_dom(const ws_domain *d) {
+    Dom m;
+    m.nx = d->g.nx;
+    m.ny = d->g.ny;
+    m.pitch = d->pitch;
+    m.zpitch = d->zpitch;
+    m.nu = d->nu;
+    m.nv = d->nv;
+    m.model = d->g.model;
+    m.friction = d->g.friction;
+    m.dx = (float)d->g.dx;
+    m.dy = (float)d->g.dy;
+    m.rdx = (float)(1.0 / d->g.dx);
+    m.rdy = (float)(1.0 / d->g.dy);
+    m.g = (float)d->g.g;
+    m.Bd = (float)d->g.Bcoef;
+    m.theta = (float)d->g.theta;
+    m.eps = (float)d->g.eps;
+    m.fcoef = (float)d->g.friction_coef;
+    m.D = d->D;
+    for (int s = 0; s < 4; ++s) {
+        m.side[s].type = d->side_type[s];
+        m.side[s].width = d->side_width[s];
+        m.side[s].ncomp = d->side_ncomp[s];
+        m.side[s].pad = 0;
+        m.side[s].tab = d->tab[s];
+    }
+    return m;
+}
+
+static dim3 tiles(const ws_domain *d) { return dim3(d->nxp / TX, d->nyp / TY); }
+
+// ----------------------------------------------------------- small kernels
+__global__ void k_corners_from_z(const float *z, float *D, int nx, int ny, int zpitch, float ws) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i <= nx && j <= ny) D[(size_t)j * zpitch + i] = ws - z[(size_t)j * (nx + 1) + i];
+}
+
+__device__ __forceinline__ float cell_Dc(const Dom &d, int i, int j) {
+    const float *r0 = d.D + (size_t)j * d.zpitch, *r1 = r0 + d.zpitch;
+    return 0.25f * ((r0[i] + r0[i + 1]) + (r1[i] + r1[i + 1]));
+}
+
+// Lake at rest: eta = max(0, -D_cell) (surface at still water or on the bottom).
+__global__ void k_rest_state(Dom d, float *e, float *p, float *q) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i >= d.nx || j >= d.ny) return;
+    size_t o = (size_t)j * d.pitch + i;
+    e[o] = fmaxf(0.f, -cell_Dc(d, i, j));
+    p[o] = 0.f;
+    q[o] = 0.f;
+}
+
+__global__ void k_set_state(Dom d, const float *w, const float *P, const float *Q, int ipitch,
+                            float ws, float *e, float *p, float *q) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i >= d.nx || j >= d.ny) return;
+    size_t o = (size_t)j * d.pitch + i, s = (size_t)j * ipitch + i;
+    e[o] = w[s] - ws;
+    p[o] = P[s];
+    q[o] = Q[s];
+}
+
+__global__ void k_read(Dom d, const float *e, const float *p, const float *q, int what, float ws,
+                       float *first, float *P, float *Q, int opitch) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i >= d.nx || j >= d.ny) return;
+    size_t o = (size_t)j * d.pitch + i, s = (size_t)j * opitch + i;
+    if (first) first[s] = what == WS_READ_H ? e[o] + cell_Dc(d, i, j) : e[o] + ws;
+    if (P) P[s] = p[o];
+    if (Q) Q[s] = q[o];
+}
+
+// Surface kept at or above the bottom, discharges desingularized where thin.
+__device__ __forceinline__ void shore_fix(const Dom &d, int i, int j, float *e, float *p, float *q) {
+    size_t o = (size_t)j * d.pitch + i;
+    float Dc = cell_Dc(d, i, j);
+    float ev = fmaxf(e[o], -Dc);
+    e[o] = ev;
+    float h = ev + Dc, h2 = h * h, h4 = h2 * h2;
+    if (h4 < d.eps) {
+        float f = 1.41421356237f * h2 * rsqrtf(h4 + d.eps);
+        p[o] *= f;
+        q[o] *= f;
+    }
+}
+
+__global__ void k_solitary(Dom d, float *e, float *p, float *q, double H, double ks, double cs,
+                           double ct, double st, double x0, double y0) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i >= d.nx || j >= d.ny) return;
+    if (!(cell_Dc(d, i, j) > 0.f)) return;
+    double x = (i + 0.5) * d.dx, y = (j + 0.5) * d.dy;
+    double sc = 1.0 / cosh(ks * ((x - x0) * ct + (y - y0) * st));
+    double eta = H * sc * sc;
+    size_t o = (size_t)j * d.pitch + i;
+    e[o] += (float)eta;
+    p[o] += (float)(cs * eta * ct);
+    q[o] += (float)(cs * eta * st);
+}
+
+__global__ void k_edit_water(Dom d, float *e, float *p, float *q, double x0, double y0, double amp,
+                             double sigma) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i >= d.nx || j >= d.ny) return;
+    double x = (i + 0.5) * d.dx - x0, y = (j + 0.5) * d.dy - y0;
+    size_t o = (size_t)j * d.pitch + i;
+    e[o] += (float)(amp * exp(-(x * x + y * y) / (2.0 * sigma * sigma)));
+    shore_fix(d, i, j, e, p, q);
+}
+
+__global__ void k_edit_terrain(Dom d, const float *Dold, float *Dnew, double x0, double y0,
+                               double amp, double sigma) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i > d.nx || j > d.ny) return;
+    double x = i * (double)d.dx - x0, y = j * (double)d.dy - y0;
+    size_t o = (size_t)j * d.zpitch + i;
+    Dnew[o] = (float)((double)Dold[o] - amp * exp(-(x * x + y * y) / (2.0 * sigma * sigma)));
+}
+
+__global__ void k_shore_fix(Dom d, float *e, float *p, float *q) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i >= d.nx || j >= d.ny) return;
+    shore_fix(d, i, j, e, p, q);
+}
+
+// Diagonal dominance of every row and column system (raw coefficients of eq. 23).
+__global__ void k_check_dd(Dom d, int *flag) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i >= d.nx || j >= d.ny) return;
+    auto dcell = [&](int a, int b) {
+        return fmaxf(0.25f * ((corner_D(d, a, b) + corner_D(d, a + 1, b)) +
+                              (corner_D(d, a, b + 1) + corner_D(d, a + 1, b + 1))), 0.f);
+    };
+    const float dc = dcell(i, j);
+    float A, B, C;
+    tri_coef(d, dc, (dcell(i + 1, j) - dcell(i - 1, j)) * 0.5f * d.rdx, d.rdx, A, B, C);
+    bool bad = !(fabsf(B) > fabsf(A) + fabsf(C));
+    tri_coef(d, dc, (dcell(i, j + 1) - dcell(i, j - 1)) * 0.5f * d.rdy, d.rdy, A, B, C);
+    bad |= !(fabsf(B) > fabsf(A) + fabsf(C));
+    if (bad) atomicOr(flag, 1);
+}
+
+// Mean still-water depth of the first interior row/column along a side.
+__global__ void k_side_depth(Dom d, int side, double *out) {
+    __shared__ double part[256];
+    const bool xs = side < 2;
+    const int n = xs ? d.ny : d.nx;
+    double s = 0.0;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        int i = xs ? (side == 0 ? 0 : d.nx - 1) : k;
+        int j = xs ? k : (side == 2 ? 0 : d.ny - 1);
+        s += fmaxf(cell_Dc(d, i, j), 0.f);
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = part[0] / n;
+}
+
+static dim3 cells_grid(int nx, int ny) { return dim3((nx + 255) / 256, ny); }
+
+// ------------------------------------------------------------------ API
+extern "C" ws_status ws_domain_init(const ws_grid *g, const float *z_corners_dev, void *workspace_dev,
+                                    size_t workspace_bytes, void *stream, ws_domain **out) {
+    if (!out) return fail(WS_EINVAL, "ws_domain_init: out is NULL");
+    *out = nullptr;
+    if (!grid_ok(g)) return fail(WS_EINVAL, "ws_domain_init: invalid grid parameters");
+    if (!z_corners_dev || !workspace_dev) return fail(WS_EINVAL, "ws_domain_init: NULL device pointer");
+    if (((uintptr_t)workspace_dev & 255) != 0) return fail(WS_EINVAL, "ws_domain_init: workspace not 256-byte aligned");
+    Layout L = layout(g);
+    if (L.nu > NRED_MAX || L.nv > NRED_MAX) return fail(WS_EINVAL, "ws_domain_init: grid too large (max %d x %d)", NRED_MAX / 2 * TX, NRED_MAX / 2 * TY);
+    if (workspace_bytes < L.total) return fail(WS_ENOMEM, "ws_domain_init: workspace %zu < %zu bytes", workspace_bytes, L.total);
+    ws_domain *d = new (std::nothrow) ws_domain();
+    if (!d) return fail(WS_ENOMEM, "ws_domain_init: host allocation failed");
+    d->g = *g;
+    d->nxp = L.nxp; d->nyp = L.nyp; d->pitch = L.pitch; d->zpitch = L.zpitch; d->nu = L.nu; d->nv = L.nv;
+    d->base = (char *)workspace_dev;
+    d->bytes = workspace_bytes;
+    char *p = d->base;
+    auto take = [&](size_t n) { char *r = p; p += n; return r; };
+    for (int b = 0; b < 3; ++b)
+        for (int f = 0; f < 3; ++f) d->st[b][f] = (float *)take(L.field);
+    d->rx = (float *)take(L.field);
+    d->ry = (float *)take(L.field);
+    for (int f = 0; f < 3; ++f) d->S[f] = (float *)take(L.field);
+    for (int s = 0; s < 3; ++s)
+        for (int f = 0; f < 5; ++f) d->hist[s][f] = (float *)take(L.field);
+    d->D = (float *)take(L.corners);
+    d->Dnew = (float *)take(L.corners);
+    d->redx = (float4 *)take(L.redx);
+    d->redy = (float4 *)take(L.redy);
+    d->solx = (float *)take(L.solx);
+    d->soly = (float *)take(L.soly);
+    for (int s = 0; s < 4; ++s) d->tab[s] = (double *)take(L.tabs);
+    char *misc = take(L.misc);
+    d->health = (int *)misc;
+    d->scal = (double *)(misc + 64);
+    for (int s = 0; s < 4; ++s) { d->side_type[s] = WS_BC_SOLID; d->side_width[s] = 2; }
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemsetAsync(d->base, 0, L.total, st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_corners_from_z, dim3((g->nx + 1 + 255) / 256, g->ny + 1), dim3(256), 0, st,
+                           z_corners_dev, d->D, g->nx, g->ny, d->zpitch, (float)g->still_water);
+        Dom m = make_dom(d);
+        hipLaunchKernelGGL(k_rest_state, cells_grid(g->nx, g->ny), dim3(256), 0, st, m, d->st[0][0],
+                           d->st[0][1], d->st[0][2]);
+        hipLaunchKernelGGL(k_check_dd, cells_grid(g->nx, g->ny), dim3(256), 0, st, m, d->health);
+        e = hipGetLastError();
+    }
+    int flag = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&flag, d->health, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess && flag) e = hipMemsetAsync(d->health, 0, sizeof(int), st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        delete d;
+        return fail(WS_EHIP, "ws_domain_init: %s", hipGetErrorString(e));
+    }
+    if (flag) {
+        delete d;
+        return fail(WS_ENOTDD, "ws_domain_init: bathymetry too steep for the grid (eq. 23 not diagonally dominant)");
+    }
+    d->cur = 0;
+    d->step = 0;
+    d->t = 0.0;
+    *out = d;
+    return WS_OK;
+}
+
+static void prof_clear(ws_domain *d) {
+    for (auto &e : d->prof) {
+        (void)hipEventDestroy(e.second.first);
+        (void)hipEventDestroy(e.second.second);
+    }
+    d->prof.clear();
+}
+
+extern "C" ws_status ws_domain_destroy(ws_domain *d) {
+    if (d) prof_clear(d);
+    delete d;
+    return WS_OK;
+}
+
+extern "C" ws_status ws_profile_enable(ws_domain *d, int32_t on) {
+    if (!d) return fail(WS_EINVAL, "ws_profile_enable: NULL domain");
+    d->prof_on = on != 0;
+    return WS_OK;
+}
+
+extern "C" ws_status ws_profile_collect(ws_domain *d, void *stream, double *total_ms, int64_t *launches,
+                                        int32_t n) {
+    if (!d || n < 0 || (n > 0 && (!total_ms || !launches))) return fail(WS_EINVAL, "ws_profile_collect: bad argument");
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    for (auto &e : d->prof) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e.second.first, e.second.second));
+        if (e.first < n) {
+            total_ms[e.first] += ms;
+            launches[e.first] += 1;
+        }
+    }
+    prof_clear(d);
+    return WS_OK;
+}
+
+// Event pair around one launch when profiling is on.
+struct ProfScope {
+    ws_domain *d;
+    hipStream_t st;
+    int cls;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(ws_domain *d_, hipStream_t s, int c) : d(d_), st(s), cls(c) {
+        if (!d->prof_on) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
+        (void)hipEventRecord(a, st);
+    }
+    ~ProfScope() {
+        if (!a) return;
+        (void)hipEventRecord(b, st);
+        d->prof.push_back({cls, {a, b}});
+    }
+};
+
+extern "C" ws_status ws_set_boundary(ws_domain *d, int32_t side, const ws_boundary *b) {
+    if (!d || !b || side < 0 || side > 3) return fail(WS_EINVAL, "ws_set_boundary: bad argument");
+    if (b->type < 0 || b->type > 2) return fail(WS_EINVAL, "ws_set_boundary: bad type %d", b->type);
+    const int nc = b->type == WS_BC_WAVES ? b->n_comp : 0;
+    if (nc < 0 || nc > MAXC) return fail(WS_EINVAL, "ws_set_boundary: n_comp %d out of range", b->n_comp);
+    if (b->type == WS_BC_SPONGE && b->width_cells < 1) return fail(WS_EINVAL, "ws_set_boundary: sponge width < 1");
+    if (nc > 0 && (!b->amp || !b->period || !b->theta_rad)) return fail(WS_EINVAL, "ws_set_boundary: NULL component array");
+    d->side_type[side] = b->type;
+    d->side_width[side] = b->width_cells;
+    d->side_ncomp[side] = 0;
+    double dref = b->ref_depth;
+    if (nc > 0 && !(dref > 0.0)) {
+        Dom m = make_dom(d);
+        hipLaunchKernelGGL(k_side_depth, dim3(1), dim3(256), 0, 0, m, side, d->scal);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpy(&dref, d->scal, sizeof(double), hipMemcpyDeviceToHost));
+    }
+    if (nc > 0 && !(dref > 0.0)) return fail(WS_EINVAL, "ws_set_boundary: no positive depth along the side");
+    std::vector<double> tab((size_t)MAXC * TABW, 0.0);
+    const double g = d->g.g;
+    for (int m = 0; m < nc; ++m) {
+        if (!(b->period[m] > 0.0)) return fail(WS_EINVAL, "ws_set_boundary: period must be > 0");
+        const double om = 2.0 * M_PI / b->period[m];
+        // Eckart's approximation of the linear dispersion relation (eq. 29)
+        const double k = om * om / g * std::sqrt(1.0 / std::tanh(om * om * dref / g));
+        const double c = om / k, cth = std::cos(b->theta_rad[m]), sth = std::sin(b->theta_rad[m]);
+        double *r = &tab[(size_t)m * TABW];
+        r[0] = b->amp[m];
+        r[1] = om;
+        r[2] = k * cth;
+        r[3] = k * sth;
+        r[4] = c * cth;
+        r[5] = c * sth;
+        r[6] = b->phase ? b->phase[m] : 0.0;
+    }
+    HIPCHK(hipMemcpy(d->tab[side], tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+    d->side_ncomp[side] = nc;
+    return WS_OK;
+}
+
+extern "C" ws_status ws_set_state(ws_domain *d, const float *w, const float *P, const float *Q,
+                                  int32_t pitch, double t, void *stream) {
+    if (!d || !w || !P || !Q || pitch < d->g.nx) return fail(WS_EINVAL, "ws_set_state: bad argument");
+    Dom m = make_dom(d);
+    hipLaunchKernelGGL(k_set_state, cells_grid(d->g.nx, d->g.ny), dim3(256), 0, (hipStream_t)stream, m, w, P,
+                       Q, pitch, (float)d->g.still_water, d->st[d->cur][0], d->st[d->cur][1], d->st[d->cur][2]);
+    HIPCHK(hipGetLastError());
+    d->t = t;
+    d->step = 0;
+    return WS_OK;
+}
+
+extern "C" ws_status ws_read(ws_domain *d, int32_t what, float *first, float *P, float *Q,
+                             int32_t pitch, void *stream) {
+    if (!d || pitch < d->g.nx || (what != WS_READ_W && what != WS_READ_H)) return fail(WS_EINVAL, "ws_read: bad argument");
+    Dom m = make_dom(d);
+    hipLaunchKernelGGL(k_read, cells_grid(d->g.nx, d->g.ny), dim3(256), 0, (hipStream_t)stream, m,
+                       d->st[d->cur][0], d->st[d->cur][1], d->st[d->cur][2], what, (float)d->g.still_water,
+                       first, P, Q, pitch);
+    HIPCHK(hipGetLastError());
+    return WS_OK;
+}
+
+extern "C" ws_status ws_add_solitary(ws_domain *d, double H, double theta, double x0, double y0,
+                                     void *stream) {
+    if (!d) return fail(WS_EINVAL, "ws_add_solitary: NULL domain");
+    hipStream_t st = (hipStream_t)stream;
+    // still water depth of the bilinear bottom at (x0, y0)
+    double fx = x0 / d->g.dx, fy = y0 / d->g.dy;
+    int ci = (int)std::floor(fx), cj = (int)std::floor(fy);
+    ci = ci < 0 ? 0 : (ci > d->g.nx - 1 ? d->g.nx - 1 : ci);
+    cj = cj < 0 ? 0 : (cj > d->g.ny - 1 ? d->g.ny - 1 : cj);
+    float c[4];
+    HIPCHK(hipStreamSynchronize(st));
+    for (int k = 0; k < 4; ++k)
+        HIPCHK(hipMemcpy(&c[k], d->D + (size_t)(cj + k / 2) * d->zpitch + ci + k % 2, sizeof(float),
+                         hipMemcpyDeviceToHost));
+    double ax = fx - ci, ay = fy - cj;
+    double dep = (1 - ax) * (1 - ay) * c[0] + ax * (1 - ay) * c[1] + (1 - ax) * ay * c[2] + ax * ay * c[3];
+    if (!(dep > 0.0) || !(H + dep > 0.0)) return fail(WS_EINVAL, "ws_add_solitary: no positive depth at the crest");
+    const double ks = std::sqrt(3.0 * std::fabs(H) / (4.0 * dep * dep * dep));  // eq. 35
+    const double cs = std::sqrt(d->g.g * (H + dep));                            // eq. 36
+    Dom m = make_dom(d);
+    hipLaunchKernelGGL(k_solitary, cells_grid(d->g.nx, d->g.ny), dim3(256), 0, st, m, d->st[d->cur][0],
+                       d->st[d->cur][1], d->st[d->cur][2], H, ks, cs, std::cos(theta), std::sin(theta), x0, y0);
+    HIPCHK(hipGetLastError());
+    return WS_OK;
+}
+
+extern "C" ws_status ws_apply_edit(ws_domain *d, int32_t kind, double x0, double y0, double amp,
+                                   double sigma, void *stream) {
+    if (!d || !(sigma > 0.0)) return fail(WS_EINVAL, "ws_apply_edit: bad argument");
+    hipStream_t st = (hipStream_t)stream;
+    Dom m = make_dom(d);
+    float *e = d->st[d->cur][0], *p = d->st[d->cur][1], *q = d->st[d->cur][2];
+    if (kind == WS_EDIT_ADD_WATER) {
+        hipLaunchKernelGGL(k_edit_water, cells_grid(d->g.nx, d->g.ny), dim3(256), 0, st, m, e, p, q, x0, y0,
+                           amp, sigma);
+        HIPCHK(hipGetLastError());
+        return WS_OK;
+    }
+    if (kind != WS_EDIT_RAISE_TERRAIN) return fail(WS_EINVAL, "ws_apply_edit: bad kind %d", kind);
+    hipLaunchKernelGGL(k_edit_terrain, cells_grid(d->g.nx + 1, d->g.ny + 1), dim3(256), 0, st, m, d->D,
+                       d->Dnew, x0, y0, amp, sigma);
+    Dom mn = m;
+    mn.D = d->Dnew;
+    HIPCHK(hipMemsetAsync(d->scal, 0, sizeof(int), st));
+    hipLaunchKernelGGL(k_check_dd, cells_grid(d->g.nx, d->g.ny), dim3(256), 0, st, mn, (int *)d->scal);
+    HIPCHK(hipGetLastError());
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(&flag, d->scal, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (flag) return fail(WS_ENOTDD, "ws_apply_edit: terrain edit rejected (eq. 23 would lose diagonal dominance)");
+    std::swap(d->D, d->Dnew);
+    m = make_dom(d);
+    hipLaunchKernelGGL(k_shore_fix, cells_grid(d->g.nx, d->g.ny), dim3(256), 0, st, m, e, p, q);
+    HIPCHK(hipGetLastError());
+    return WS_OK;
+}
+
+// One predictor or corrector pass: stencil, then the partitioned solves.
+static ws_status run_pass(ws_domain *d, const Dom &m, StencilArgs &sa, int base, int out, double t0,
+                          double t1, bool sponge, hipStream_t st) {
+    {
+        ProfScope p(d, st, sa.kind == 2 ? WS_K_CORRECTOR : WS_K_PREDICTOR);
+        hipLaunchKernelGGL(k_stencil, tiles(d), dim3(NT), 0, st, sa);
+    }
+    SolveArgs so;
+    so.d = m;
+    so.rx = d->rx;
+    so.ry = d->ry;
+    so.redx = d->redx;
+    so.redy = d->redy;
+    so.solx = d->solx;
+    so.soly = d->soly;
+    so.eta = d->st[out][0];
+    so.pout = d->st[out][1];
+    so.qout = d->st[out][2];
+    so.pbase = d->st[base][1];
+    so.qbase = d->st[base][2];
+    so.health = d->health;
+    so.t0 = t0;
+    so.t1 = t1;
+    so.sponge = sponge ? 1 : 0;
+    {
+        ProfScope p(d, st, WS_K_REDUCE);
+        hipLaunchKernelGGL(k_reduce, tiles(d), dim3(NT), 0, st, so);
+    }
+    {
+        ProfScope p(d, st, WS_K_PCR);
+        hipLaunchKernelGGL(k_pcr, dim3(d->g.ny + d->g.nx), dim3(NT), 0, st, so);
+    }
+    {
+        ProfScope p(d, st, WS_K_EXPAND);
+        hipLaunchKernelGGL(k_expand, tiles(d), dim3(NT), 0, st, so);
+    }
+    HIPCHK(hipGetLastError());
+    return WS_OK;
+}
+
+extern "C" ws_status ws_advance(ws_domain *d, int64_t nsteps, void *stream) {
+    if (!d || nsteps < 0) return fail(WS_EINVAL, "ws_advance: bad argument");
+    hipStream_t st = (hipStream_t)stream;
+    const Dom m = make_dom(d);
+    const ws_grid &g = d->g;
+    float x0 = 0.f, x1 = 0.f, x2 = 0.f;
+    if (g.fstar_extrap == 2) { x0 = 2.f; x1 = -3.f; x2 = 1.f; }
+    else if (g.fstar_extrap == 1) { x0 = 1.f; x1 = -1.f; }
+    for (int64_t n = 0; n < nsteps; ++n) {
+        const int64_t s = d->step + 1;
+        const bool euler = s <= 2;
+        const int K = euler ? 0 : g.n_corr;
+        const int n0 = (int)((s - 1) % 3), n1 = (int)((s + 1) % 3), n2 = (int)(s % 3);
+        const double t0 = d->t, t1 = d->t + g.dt;
+        const int a = d->cur, b = (a + 1) % 3, c = (a + 2) % 3;  // base and the two estimates
+        StencilArgs sa;
+        std::memset(&sa, 0, sizeof sa);
+        sa.d = m;
+        sa.ein = d->st[a][0]; sa.pin = d->st[a][1]; sa.qin = d->st[a][2];
+        sa.eout = d->st[b][0];
+        sa.rx = d->rx; sa.ry = d->ry;
+        sa.hE = d->hist[n0][0]; sa.hF = d->hist[n0][1]; sa.hG = d->hist[n0][2];
+        sa.hFs = d->hist[n0][3]; sa.hGs = d->hist[n0][4];
+        sa.E1 = d->hist[n1][0]; sa.F1 = d->hist[n1][1]; sa.G1 = d->hist[n1][2];
+        sa.Fs1 = d->hist[n1][3]; sa.Gs1 = d->hist[n1][4];
+        sa.E2 = d->hist[n2][0]; sa.F2 = d->hist[n2][1]; sa.G2 = d->hist[n2][2];
+        sa.Fs2 = d->hist[n2][3]; sa.Gs2 = d->hist[n2][4];
+        sa.Se = d->S[0]; sa.SU = d->S[1]; sa.SV = d->S[2];
+        sa.t = t0;
+        sa.dt = (float)g.dt;
+        sa.x0 = x0; sa.x1 = x1; sa.x2 = x2;
+        sa.kind = euler ? 0 : 1;
+        sa.write_S = (!euler && K > 0) ? 1 : 0;
+        ws_status r = run_pass(d, m, sa, a, b, t0, t1, K == 0, st);
+        if (r != WS_OK) return r;
+        int in = b;
+        for (int k = 1; k <= K; ++k) {
+            const int out = in == b ? c : b;
+            sa.ein = d->st[in][0]; sa.pin = d->st[in][1]; sa.qin = d->st[in][2];
+            sa.eout = d->st[out][0];
+            sa.t = t1;
+            sa.kind = 2;
+            sa.write_S = 0;
+            r = run_pass(d, m, sa, a, out, t0, t1, k == K, st);
+            if (r != WS_OK) return r;
+            in = out;
+        }
+        d->cur = in;
+        d->step = s;
+        d->t = t1;
+    }
+    return WS_OK;
+}
+
+extern "C" ws_status ws_query(ws_domain *d, void *stream, int64_t *step, double *t, int32_t *health) {
+    if (!d) return fail(WS_EINVAL, "ws_query: NULL domain");
+    hipStream_t st = (hipStream_t)stream;
+    int h = 0;
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemcpy(&h, d->health, sizeof(int), hipMemcpyDeviceToHost));
+    if (step) *step = d->step;
+    if (t) *t = d->t;
+    if (health) *health = h;
+    if (h) return fail(WS_ENONFINITE, "ws_query: non-finite state");
+    return WS_OK;
+}

@@ -1,0 +1,213 @@
+"""ctypes binding of libwavestep.so (C ABI in include/wavestep.h).
+
+Argument marshalling only: every step of the solver runs in the library's HIP
+kernels.  PyTorch provides the device memory (the workspace is a uint8 tensor
+owned by the Domain object) and the stream (torch's current stream by
+default).  The library must be built (``python -m paper_1611_05984_amd.build``
+or ``__graft_entry__.build()``); loading fails with an error otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwavestep.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOTDD, ENONFINITE, EBUSY = 0, -1, -2, -3, -4, -5, -6
+BSNQ, NLSW = 0, 1
+FRIC_NONE, FRIC_QUAD, FRIC_MANNING = 0, 1, 2
+WEST, EAST, SOUTH, NORTH = 0, 1, 2, 3
+SOLID, SPONGE, WAVES = 0, 1, 2
+EDIT_WATER, EDIT_TERRAIN = 0, 1
+READ_W, READ_H = 0, 1
+K_PREDICTOR, K_CORRECTOR, K_REDUCE, K_PCR, K_EXPAND, K_COUNT = 0, 1, 2, 3, 4, 5
+KERNEL_NAMES = ("k_stencil[predictor]", "k_stencil[corrector]", "k_reduce", "k_pcr", "k_expand")
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("n_corr", C.c_int32),
+                ("model", C.c_int32), ("friction", C.c_int32), ("fstar_extrap", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("dt", C.c_double), ("g", C.c_double),
+                ("still_water", C.c_double), ("Bcoef", C.c_double), ("theta", C.c_double),
+                ("eps", C.c_double), ("friction_coef", C.c_double)]
+
+
+class Boundary(C.Structure):
+    _fields_ = [("type", C.c_int32), ("width_cells", C.c_int32), ("n_comp", C.c_int32),
+                ("reserved", C.c_int32), ("amp", C.POINTER(C.c_double)),
+                ("period", C.POINTER(C.c_double)), ("theta_rad", C.POINTER(C.c_double)),
+                ("phase", C.POINTER(C.c_double)), ("ref_depth", C.c_double)]
+
+
+class WaveStepError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("wavestep status %d: %s" % (status, msg))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libwavestep.so is not built (%s); run paper_1611_05984_amd/build.py"
+                               % LIB_PATH)
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, f64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t
+        sigs = {
+            "ws_grid_defaults": (None, [C.POINTER(Grid), i32, i32]),
+            "ws_workspace_bytes": (sz, [C.POINTER(Grid)]),
+            "ws_domain_init": (C.c_int, [C.POINTER(Grid), vp, vp, sz, vp, C.POINTER(vp)]),
+            "ws_domain_destroy": (C.c_int, [vp]),
+            "ws_set_boundary": (C.c_int, [vp, i32, C.POINTER(Boundary)]),
+            "ws_set_state": (C.c_int, [vp, vp, vp, vp, i32, f64, vp]),
+            "ws_add_solitary": (C.c_int, [vp, f64, f64, f64, f64, vp]),
+            "ws_advance": (C.c_int, [vp, i64, vp]),
+            "ws_read": (C.c_int, [vp, i32, vp, vp, vp, i32, vp]),
+            "ws_apply_edit": (C.c_int, [vp, i32, f64, f64, f64, f64, vp]),
+            "ws_query": (C.c_int, [vp, vp, C.POINTER(i64), C.POINTER(f64), C.POINTER(i32)]),
+            "ws_last_error": (C.c_char_p, []),
+            "ws_profile_enable": (C.c_int, [vp, i32]),
+            "ws_profile_collect": (C.c_int, [vp, vp, C.POINTER(f64), C.POINTER(i64), i32]),
+        }
+        for name, (res, args) in sigs.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status, what=""):
+    if status != OK:
+        raise WaveStepError(status, (what + ": " if what else "") +
+                            lib().ws_last_error().decode(errors="replace"))
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def grid(nx, ny, dx, dy, dt, **kw) -> Grid:
+    g = Grid()
+    lib().ws_grid_defaults(C.byref(g), int(nx), int(ny))
+    g.dx, g.dy, g.dt = float(dx), float(dy), float(dt)
+    for k, v in kw.items():
+        setattr(g, k, v)
+    return g
+
+
+def workspace_bytes(g: Grid) -> int:
+    return int(lib().ws_workspace_bytes(C.byref(g)))
+
+
+class Domain:
+    """One domain resident on the GPU.
+
+    z: bottom elevation at the (ny+1) x (nx+1) cell corners (numpy or torch).
+    Fields are exchanged as float32 CUDA tensors of shape (ny, nx).
+    """
+
+    def __init__(self, nx, ny, dx, dy, dt, z, device="cuda", stream=None, **params):
+        import torch
+        self.device = torch.device(device)
+        self.g = grid(nx, ny, dx, dy, dt, **params)
+        self.nx, self.ny = int(nx), int(ny)
+        nbytes = workspace_bytes(self.g)
+        if nbytes == 0:
+            raise WaveStepError(EINVAL, "invalid grid parameters")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        zt = torch.as_tensor(np.asarray(z) if not torch.is_tensor(z) else z,
+                             dtype=torch.float32).to(self.device).contiguous()
+        if zt.numel() != (ny + 1) * (nx + 1):
+            raise ValueError("z must hold (ny+1)*(nx+1) corner values")
+        h = C.c_void_p()
+        _check(lib().ws_domain_init(C.byref(self.g), _dptr(zt), _dptr(self.workspace), nbytes,
+                                    _stream(stream), C.byref(h)), "ws_domain_init")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ws_domain_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_boundary(self, side, kind, width=2, amp=(), period=(), theta=(), phase=None,
+                     ref_depth=0.0):
+        n = len(amp)
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in
+                (amp, period, theta, phase if phase is not None else np.zeros(n))]
+        ptrs = [a.ctypes.data_as(C.POINTER(C.c_double)) for a in arrs]
+        b = Boundary(int(kind), int(width), n, 0, *ptrs, float(ref_depth))
+        _check(lib().ws_set_boundary(self._h, int(side), C.byref(b)), "ws_set_boundary")
+
+    def set_state(self, w, P, Q, t=0.0, stream=None):
+        import torch
+        ts = [torch.as_tensor(a, dtype=torch.float32).to(self.device).contiguous() for a in (w, P, Q)]
+        for a in ts:
+            assert a.shape == (self.ny, self.nx), a.shape
+        _check(lib().ws_set_state(self._h, *[_dptr(a) for a in ts], self.nx, float(t),
+                                  _stream(stream)), "ws_set_state")
+        self._keep = ts   # keep the inputs alive until the copy kernel has run
+
+    def add_solitary(self, H, theta, x0, y0, stream=None):
+        _check(lib().ws_add_solitary(self._h, H, theta, x0, y0, _stream(stream)), "ws_add_solitary")
+
+    def advance(self, n, stream=None):
+        _check(lib().ws_advance(self._h, int(n), _stream(stream)), "ws_advance")
+
+    def read(self, what=READ_W, stream=None):
+        import torch
+        out = [torch.empty((self.ny, self.nx), dtype=torch.float32, device=self.device)
+               for _ in range(3)]
+        _check(lib().ws_read(self._h, int(what), *[_dptr(a) for a in out], self.nx,
+                             _stream(stream)), "ws_read")
+        return tuple(out)
+
+    def state_numpy(self, what=READ_W):
+        import torch
+        out = self.read(what)
+        torch.cuda.current_stream().synchronize()
+        return tuple(a.cpu().numpy() for a in out)
+
+    def apply_edit(self, kind, x0, y0, amp, sigma, stream=None):
+        """Returns the status (0, or ENOTDD for a rejected terrain edit)."""
+        st = lib().ws_apply_edit(self._h, int(kind), x0, y0, amp, sigma, _stream(stream))
+        if st not in (OK, ENOTDD):
+            _check(st, "ws_apply_edit")
+        return st
+
+    def query(self, stream=None):
+        step, t, health = C.c_int64(), C.c_double(), C.c_int32()
+        st = lib().ws_query(self._h, _stream(stream), C.byref(step), C.byref(t), C.byref(health))
+        if st not in (OK, ENONFINITE):
+            _check(st, "ws_query")
+        return step.value, t.value, health.value
+
+    def profile(self, on=True):
+        _check(lib().ws_profile_enable(self._h, 1 if on else 0), "ws_profile_enable")
+
+    def profile_collect(self, stream=None):
+        """{kernel class: (summed ms, launches)} since the last collection."""
+        ms = (C.c_double * K_COUNT)()
+        n = (C.c_int64 * K_COUNT)()
+        _check(lib().ws_profile_collect(self._h, _stream(stream), ms, n, K_COUNT), "ws_profile_collect")
+        return {KERNEL_NAMES[k]: (ms[k], n[k]) for k in range(K_COUNT)}
