@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--n", type=int, default=4096, help="grid side (cells)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a 256 MiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -82,6 +84,13 @@ def main():
     from paper_1611_05984_amd import workloads as wl
 
     torch.cuda.set_device(0)
+    if args.copy_calib:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = wl.config3(n=args.n)
     D = ws.Domain(w.nx, w.ny, w.dx, w.dy, w.dt, w.z, device="cuda:0")
     for s, side in enumerate(w.sides):

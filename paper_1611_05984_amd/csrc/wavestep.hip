@@ -50,6 +50,8 @@ struct ws_domain {
     float *hist[3][5];             // [slot][E, F, G, F*, G*]
     float4 *redx, *redy;
     float *solx, *soly;
+    float *ghost[2];               // wave-maker ghosts at t^n, t^{n+1}
+    int gl;                        // ghost positions per layer
     double *tab[4];                // wave tables
     int *health;
     double *scal;                  // small device scratch (reductions)
@@ -65,8 +67,8 @@ static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 static int roundup(int x, int m) { return (x + m - 1) / m * m; }
 
 struct Layout {
-    int nxp, nyp, pitch, zpitch, nu, nv;
-    size_t field, corners, redx, redy, solx, soly, tabs, misc, total;
+    int nxp, nyp, pitch, zpitch, nu, nv, gl;
+    size_t field, corners, redx, redy, solx, soly, ghost, tabs, misc, total;
 };
 
 static bool grid_ok(const ws_grid *g) {
@@ -82,17 +84,20 @@ static Layout layout(const ws_grid *g) {
     L.nyp = roundup(g->ny, TY);
     L.pitch = L.nxp;
     L.zpitch = roundup(g->nx + 1, 64);
-    L.nu = 2 * (L.nxp / TX);
+    L.nu = 2 * (L.nxp / MX);
     L.nv = 2 * (L.nyp / TY);
+    L.gl = (g->nx > g->ny ? g->nx : g->ny) + 4;
     L.field = align256(sizeof(float) * (size_t)L.nyp * L.pitch);
     L.corners = align256(sizeof(float) * (size_t)(g->ny + 1) * L.zpitch);
     L.redx = align256(sizeof(float4) * (size_t)L.nyp * L.nu);
     L.redy = align256(sizeof(float4) * (size_t)L.nxp * L.nv);
     L.solx = align256(sizeof(float) * (size_t)L.nyp * L.nu);
     L.soly = align256(sizeof(float) * (size_t)L.nxp * L.nv);
+    L.ghost = align256(sizeof(float) * 4 * 2 * 3 * (size_t)L.gl);
     L.tabs = align256(sizeof(double) * MAXC * TABW);
     L.misc = 256;
-    L.total = 29 * L.field + 2 * L.corners + L.redx + L.redy + L.solx + L.soly + 4 * L.tabs + L.misc;
+    L.total = 29 * L.field + 2 * L.corners + L.redx + L.redy + L.solx + L.soly + 2 * L.ghost +
+              4 * L.tabs + L.misc;
     return L;
 }
 
@@ -127,6 +132,8 @@ static Dom make_dom(const ws_domain *d) {
     m.nv = d->nv;
     m.model = d->g.model;
     m.friction = d->g.friction;
+    m.gl = d->gl;
+    m.gh = d->ghost[0];
     m.dx = (float)d->g.dx;
     m.dy = (float)d->g.dy;
     m.rdx = (float)(1.0 / d->g.dx);
@@ -291,12 +298,13 @@ extern "C" ws_status ws_domain_init(const ws_grid *g, const float *z_corners_dev
     if (!z_corners_dev || !workspace_dev) return fail(WS_EINVAL, "ws_domain_init: NULL device pointer");
     if (((uintptr_t)workspace_dev & 255) != 0) return fail(WS_EINVAL, "ws_domain_init: workspace not 256-byte aligned");
     Layout L = layout(g);
-    if (L.nu > NRED_MAX || L.nv > NRED_MAX) return fail(WS_EINVAL, "ws_domain_init: grid too large (max %d x %d)", NRED_MAX / 2 * TX, NRED_MAX / 2 * TY);
+    if (L.nu > NRED_MAX || L.nv > NRED_MAX) return fail(WS_EINVAL, "ws_domain_init: grid too large (max %d x %d)", NRED_MAX / 2 * MX, NRED_MAX / 2 * TY);
     if (workspace_bytes < L.total) return fail(WS_ENOMEM, "ws_domain_init: workspace %zu < %zu bytes", workspace_bytes, L.total);
     ws_domain *d = new (std::nothrow) ws_domain();
     if (!d) return fail(WS_ENOMEM, "ws_domain_init: host allocation failed");
     d->g = *g;
     d->nxp = L.nxp; d->nyp = L.nyp; d->pitch = L.pitch; d->zpitch = L.zpitch; d->nu = L.nu; d->nv = L.nv;
+    d->gl = L.gl;
     d->base = (char *)workspace_dev;
     d->bytes = workspace_bytes;
     char *p = d->base;
@@ -314,6 +322,8 @@ extern "C" ws_status ws_domain_init(const ws_grid *g, const float *z_corners_dev
     d->redy = (float4 *)take(L.redy);
     d->solx = (float *)take(L.solx);
     d->soly = (float *)take(L.soly);
+    d->ghost[0] = (float *)take(L.ghost);
+    d->ghost[1] = (float *)take(L.ghost);
     for (int s = 0; s < 4; ++s) d->tab[s] = (double *)take(L.tabs);
     char *misc = take(L.misc);
     d->health = (int *)misc;
@@ -524,15 +534,20 @@ extern "C" ws_status ws_apply_edit(ws_domain *d, int32_t kind, double x0, double
     return WS_OK;
 }
 
+static dim3 strips(const ws_domain *d) {
+    const int ns = (d->g.nx + SO - 1) / SO;
+    return dim3((ns + SWG - 1) / SWG, (d->g.ny + SY - 1) / SY);
+}
+
 // One predictor or corrector pass: stencil, then the partitioned solves.
-static ws_status run_pass(ws_domain *d, const Dom &m, StencilArgs &sa, int base, int out, double t0,
-                          double t1, bool sponge, hipStream_t st) {
+static ws_status run_pass(ws_domain *d, StencilArgs &sa, int base, int out, bool sponge,
+                          hipStream_t st) {
     {
         ProfScope p(d, st, sa.kind == 2 ? WS_K_CORRECTOR : WS_K_PREDICTOR);
-        hipLaunchKernelGGL(k_stencil, tiles(d), dim3(NT), 0, st, sa);
+        hipLaunchKernelGGL(k_stencil, strips(d), dim3(64 * SWG), 0, st, sa);
     }
     SolveArgs so;
-    so.d = m;
+    so.d = sa.d;
     so.rx = d->rx;
     so.ry = d->ry;
     so.redx = d->redx;
@@ -544,9 +559,9 @@ static ws_status run_pass(ws_domain *d, const Dom &m, StencilArgs &sa, int base,
     so.qout = d->st[out][2];
     so.pbase = d->st[base][1];
     so.qbase = d->st[base][2];
+    so.gh0 = d->ghost[0];
+    so.gh1 = d->ghost[1];
     so.health = d->health;
-    so.t0 = t0;
-    so.t1 = t1;
     so.sponge = sponge ? 1 : 0;
     {
         ProfScope p(d, st, WS_K_REDUCE);
@@ -554,7 +569,8 @@ static ws_status run_pass(ws_domain *d, const Dom &m, StencilArgs &sa, int base,
     }
     {
         ProfScope p(d, st, WS_K_PCR);
-        hipLaunchKernelGGL(k_pcr, dim3(d->g.ny + d->g.nx), dim3(NT), 0, st, so);
+        const int nred = d->nu > d->nv ? d->nu : d->nv;
+        hipLaunchKernelGGL(k_pcr, dim3(d->g.ny + d->g.nx), dim3(PCR_NT), sizeof(float4) * nred, st, so);
     }
     {
         ProfScope p(d, st, WS_K_EXPAND);
@@ -578,6 +594,13 @@ extern "C" ws_status ws_advance(ws_domain *d, int64_t nsteps, void *stream) {
         const int K = euler ? 0 : g.n_corr;
         const int n0 = (int)((s - 1) % 3), n1 = (int)((s + 1) % 3), n2 = (int)(s % 3);
         const double t0 = d->t, t1 = d->t + g.dt;
+        bool makers = false;
+        for (int q = 0; q < 4; ++q) makers |= d->side_type[q] == WS_BC_WAVES;
+        if (makers) {
+            const int n = 8 * d->gl;
+            hipLaunchKernelGGL(k_ghosts, dim3((n + 255) / 256), dim3(256), 0, st, m, d->ghost[0], t0);
+            hipLaunchKernelGGL(k_ghosts, dim3((n + 255) / 256), dim3(256), 0, st, m, d->ghost[1], t1);
+        }
         const int a = d->cur, b = (a + 1) % 3, c = (a + 2) % 3;  // base and the two estimates
         StencilArgs sa;
         std::memset(&sa, 0, sizeof sa);
@@ -592,22 +615,22 @@ extern "C" ws_status ws_advance(ws_domain *d, int64_t nsteps, void *stream) {
         sa.E2 = d->hist[n2][0]; sa.F2 = d->hist[n2][1]; sa.G2 = d->hist[n2][2];
         sa.Fs2 = d->hist[n2][3]; sa.Gs2 = d->hist[n2][4];
         sa.Se = d->S[0]; sa.SU = d->S[1]; sa.SV = d->S[2];
-        sa.t = t0;
+        sa.d.gh = d->ghost[0];
         sa.dt = (float)g.dt;
         sa.x0 = x0; sa.x1 = x1; sa.x2 = x2;
         sa.kind = euler ? 0 : 1;
         sa.write_S = (!euler && K > 0) ? 1 : 0;
-        ws_status r = run_pass(d, m, sa, a, b, t0, t1, K == 0, st);
+        ws_status r = run_pass(d, sa, a, b, K == 0, st);
         if (r != WS_OK) return r;
         int in = b;
         for (int k = 1; k <= K; ++k) {
             const int out = in == b ? c : b;
             sa.ein = d->st[in][0]; sa.pin = d->st[in][1]; sa.qin = d->st[in][2];
             sa.eout = d->st[out][0];
-            sa.t = t1;
+            sa.d.gh = d->ghost[1];
             sa.kind = 2;
             sa.write_S = 0;
-            r = run_pass(d, m, sa, a, out, t0, t1, k == K, st);
+            r = run_pass(d, sa, a, out, k == K, st);
             if (r != WS_OK) return r;
             in = out;
         }

@@ -11,9 +11,13 @@
 
 namespace ws {
 
-constexpr int TX = 64;        // tile width  (cells along x) = row segment length
-constexpr int TY = 16;        // tile height (cells along y) = column segment length
-constexpr int NT = 256;       // threads per tile workgroup (4 wave64)
+constexpr int TX = 64;        // solver tile width  (cells along x)
+constexpr int TY = 16;        // solver tile height (cells along y) = column segment length
+constexpr int MX = 16;        // row segment length (4 per solver tile row)
+constexpr int NT = 128;       // threads per solver tile workgroup (2 wave64)
+constexpr int SO = 62;        // stencil: output columns per 64-lane strip wave
+constexpr int SY = 32;        // stencil: rows streamed per strip wave
+constexpr int SWG = 4;        // stencil: strip waves per workgroup
 constexpr int MAXC = 256;     // wave components per side
 constexpr int TABW = 8;       // doubles per component: a, omega, kx, ky, cx, cy, phase, -
 constexpr int NRED_MAX = 2048;  // reduced unknowns per row/column system
@@ -31,11 +35,19 @@ struct Dom {
     int nx, ny, pitch, zpitch;
     int nu, nv;         // reduced unknowns of one row / one column system
     int model, friction;
+    int gl;             // ghost-buffer positions per layer: max(nx, ny) + 4
     float dx, dy, rdx, rdy;
     float g, Bd, theta, eps, fcoef;
     const float *D;     // corner still-water depth, (ny+1) rows x zpitch
+    const float *gh;    // wave-maker ghost values at the pass's time (see ghost_index)
     SideDev side[4];
 };
+
+// Wave-maker ghost values are precomputed per time level: [side][layer][pos][eta, P, Q],
+// layer 0 next to the boundary, pos = along-side cell index + 2 (covers -2 .. n+1).
+__device__ __forceinline__ size_t ghost_index(const Dom &d, int side, int layer, int pos) {
+    return (((size_t)side * 2 + layer) * d.gl + pos) * 3;
+}
 
 __device__ __forceinline__ bool is_wall(const Dom &d, int s) { return d.side[s].type != BC_WAVES; }
 
@@ -76,10 +88,11 @@ __device__ inline void wave_eval(const SideDev &s, double x, double y, double t,
 // Value of cell (i, j), inside or in the two-cell ghost ring: reflected across
 // every wall side first (normal discharge of that side changes sign), then, if
 // still behind a wave-maker side, that maker's values at the reflected
-// position.  Cells further out (tile padding) are clamped into the domain.
+// position (precomputed ghost buffer).  Cells further out (padding) are
+// clamped into the domain.
 __device__ inline void load_cell(const Dom &d, const float *__restrict__ E,
                                  const float *__restrict__ P, const float *__restrict__ Q, int i,
-                                 int j, double t, float &e, float &p, float &q) {
+                                 int j, float &e, float &p, float &q) {
     float sp = 1.f, sq = 1.f;
     if (i < 0 && is_wall(d, 0)) { i = -1 - i; sp = -sp; }
     if (i >= d.nx && is_wall(d, 1)) { i = 2 * d.nx - 1 - i; sp = -sp; }
@@ -90,7 +103,14 @@ __device__ inline void load_cell(const Dom &d, const float *__restrict__ E,
     if (!in_i) side = i < 0 ? 0 : 1;
     else if (!in_j) side = j < 0 ? 2 : 3;
     if (side >= 0 && d.side[side].type == BC_WAVES) {
-        wave_eval(d.side[side], (i + 0.5) * (double)d.dx, (j + 0.5) * (double)d.dy, t, e, p, q);
+        int layer = side == 0 ? -1 - i : side == 1 ? i - d.nx : side == 2 ? -1 - j : j - d.ny;
+        int pos = (side < 2 ? j : i) + 2;
+        layer = layer < 0 ? 0 : (layer > 1 ? 1 : layer);
+        pos = pos < 0 ? 0 : (pos >= d.gl ? d.gl - 1 : pos);
+        const float *g = d.gh + ghost_index(d, side, layer, pos);
+        e = g[0];
+        p = g[1];
+        q = g[2];
     } else {
         i = i < 0 ? 0 : (i >= d.nx ? d.nx - 1 : i);
         j = j < 0 ? 0 : (j >= d.ny ? d.ny - 1 : j);
@@ -105,9 +125,23 @@ __device__ inline void load_cell(const Dom &d, const float *__restrict__ E,
 
 // ---------------------------------------------------------------- KP07 parts
 __device__ __forceinline__ float minmod3(float a, float b, float c) {
-    if (a > 0.f && b > 0.f && c > 0.f) return fminf(a, fminf(b, c));
-    if (a < 0.f && b < 0.f && c < 0.f) return fmaxf(a, fmaxf(b, c));
-    return 0.f;
+    const float mn = fminf(a, fminf(b, c)), mx = fmaxf(a, fmaxf(b, c));
+    return mn > 0.f ? mn : (mx < 0.f ? mx : 0.f);
+}
+
+// Hardware reciprocal, reciprocal square root and square root (1 ulp); their
+// arguments here are never denormal except sqrt of a vanishing depth.
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// Lane shifts across the 64-lane wave (DPP wave_shr:1 / wave_shl:1): lane k
+// takes lane k-1 (shr) or k+1 (shl); the lane without a source takes `old`.
+__device__ __forceinline__ float shr1(float v, float old) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float shl1(float v, float old) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), 0x130, 0xf, 0xf, false));
 }
 
 struct F3 { float e, n, t; };  // surface, normal and tangential discharge at a face
@@ -121,25 +155,20 @@ __device__ __forceinline__ void reconstruct(float em, float e0, float ep, float 
     float se = minmod3(th * (e0 - em), 0.5f * (ep - em), th * (ep - e0));
     float sn = minmod3(th * (n0 - nm), 0.5f * (np - nm), th * (np - n0));
     float st = minmod3(th * (t0 - tm), 0.5f * (tp - tm), th * (tp - t0));
-    lo.e = e0 - 0.5f * se;
-    hi.e = e0 + 0.5f * se;
+    const float lo_e = e0 - 0.5f * se, hi_e = e0 + 0.5f * se;
+    const bool fix_hi = hi_e < -Dhi, fix_lo = !fix_hi && lo_e < -Dlo;
+    lo.e = fix_hi ? 2.f * e0 + Dhi : (fix_lo ? -Dlo : lo_e);
+    hi.e = fix_hi ? -Dhi : (fix_lo ? 2.f * e0 + Dlo : hi_e);
     lo.n = n0 - 0.5f * sn;
     hi.n = n0 + 0.5f * sn;
     lo.t = t0 - 0.5f * st;
     hi.t = t0 + 0.5f * st;
-    if (hi.e < -Dhi) {
-        hi.e = -Dhi;
-        lo.e = 2.f * e0 + Dhi;
-    } else if (lo.e < -Dlo) {
-        lo.e = -Dlo;
-        hi.e = 2.f * e0 + Dlo;
-    }
 }
 
 // Desingularized velocity sqrt(2) h m / sqrt(h^4 + max(h^4, eps)).
 __device__ __forceinline__ float desing(float h, float m, float eps) {
     float h2 = h * h, h4 = h2 * h2;
-    return 1.41421356237f * h * m * rsqrtf(h4 + fmaxf(h4, eps));
+    return 1.41421356237f * h * m * frsq(h4 + fmaxf(h4, eps));
 }
 
 // Central-upwind flux at a face in well-balanced ("pre-balanced") form.  With
@@ -152,25 +181,26 @@ __device__ __forceinline__ float desing(float h, float m, float eps) {
 // Returns (mass, normal momentum, tangential momentum).
 __device__ __forceinline__ void cu_flux(float g, float eps, float Df, const F3 &L, const F3 &R,
                                         float &H0, float &H1, float &H2) {
-    float hL = fmaxf(L.e + Df, 0.f), hR = fmaxf(R.e + Df, 0.f);
-    float uL = desing(hL, L.n, eps), vL = desing(hL, L.t, eps);
-    float uR = desing(hR, R.n, eps), vR = desing(hR, R.t, eps);
-    float nL = hL * uL, tL = hL * vL, nR = hR * uR, tR = hR * vR;
-    float cL = sqrtf(g * hL), cR = sqrtf(g * hR);
-    float ap = fmaxf(fmaxf(uL + cL, uR + cR), 0.f);
-    float am = fminf(fminf(uL - cL, uR - cR), 0.f);
-    if (ap - am <= 1e-10f) {
-        H0 = 0.f;
-        H1 = -0.5f * g * Df * Df;
-        H2 = 0.f;
-        return;
-    }
-    float eL = hL > 0.f ? L.e : -Df, eR = hR > 0.f ? R.e : -Df;
-    float pL = 0.5f * g * eL * (eL + 2.f * Df), pR = 0.5f * g * eR * (eR + 2.f * Df);
-    float inv = 1.f / (ap - am), apam = ap * am * inv;
-    H0 = (ap * nL - am * nR) * inv + apam * (R.e - L.e);
-    H1 = (ap * (nL * uL + pL) - am * (nR * uR + pR)) * inv + apam * (nR - nL);
-    H2 = (ap * (nL * vL) - am * (nR * vR)) * inv + apam * (tR - tL);
+    const float hL = fmaxf(L.e + Df, 0.f), hR = fmaxf(R.e + Df, 0.f);
+    const float hL2 = hL * hL, hL4 = hL2 * hL2, hR2 = hR * hR, hR4 = hR2 * hR2;
+    // eq. (14): u = m * sqrt(2) h / sqrt(h^4 + max(h^4, eps)), one factor per side
+    const float fL = 1.41421356237f * hL * frsq(hL4 + fmaxf(hL4, eps));
+    const float fR = 1.41421356237f * hR * frsq(hR4 + fmaxf(hR4, eps));
+    const float uL = fL * L.n, vL = fL * L.t, uR = fR * R.n, vR = fR * R.t;
+    const float nL = hL * uL, tL = hL * vL, nR = hR * uR, tR = hR * vR;
+    const float cL = fsqrt(g * hL), cR = fsqrt(g * hR);
+    const float ap = fmaxf(fmaxf(uL + cL, uR + cR), 0.f);
+    const float am = fminf(fminf(uL - cL, uR - cR), 0.f);
+    const float eL = hL > 0.f ? L.e : -Df, eR = hR > 0.f ? R.e : -Df;
+    const float pL = 0.5f * g * eL * (eL + 2.f * Df), pR = 0.5f * g * eR * (eR + 2.f * Df);
+    const bool dry = ap - am <= 1e-10f;
+    const float inv = frcp(dry ? 1.f : ap - am), apam = ap * am * inv;
+    const float m = (ap * nL - am * nR) * inv + apam * (R.e - L.e);
+    const float n = (ap * (nL * uL + pL) - am * (nR * uR + pR)) * inv + apam * (nR - nL);
+    const float t = (ap * (nL * vL) - am * (nR * vR)) * inv + apam * (tR - tL);
+    H0 = dry ? 0.f : m;
+    H1 = dry ? -0.5f * g * Df * Df : n;
+    H2 = dry ? 0.f : t;
 }
 
 // Row/column system coefficients of eq. 23 for one cell.

@@ -1,15 +1,18 @@
 // ws_kernels.hpp -- the gfx950 kernels of one predictor/corrector pass.
 //
 // A pass is four launches:
-//   k_stencil  one workgroup per 64x16 tile: halo-staged (LDS) state, KP07
-//              face fluxes, dispersive and friction terms, time integration;
-//              writes the new surface and the increments U* - U*^n,
-//              V* - V*^n (the solves work in delta form: T (P - P^n) =
-//              U* - U*^n, algebraically the same system, whose right-hand
-//              side is O(dt F) instead of O(P), so single precision loses
-//              far less in the solve).
-//   k_reduce   per tile: coefficients of eq. 23 from the bathymetry, and the
-//              elimination of every 64-cell row segment and 16-cell column
+//   k_stencil  column-streaming: one wave owns a strip of 64 columns (62 of
+//              them output) and walks 32 rows with a sliding register window;
+//              x-neighbours come from DPP lane shifts, so every face is
+//              reconstructed and fluxed once and no LDS or barrier is used.
+//              KP07 face fluxes, bottom source, dispersive and friction
+//              terms, time integration.  Writes the new surface and the
+//              increments U* - U*^n, V* - V*^n: the solves work in delta
+//              form, T (P - P^n) = U* - U*^n, algebraically the same system,
+//              whose right-hand side is O(dt F) instead of O(P), so single
+//              precision loses far less in the solve.
+//   k_reduce   per 64x16 tile: coefficients of eq. 23 from the bathymetry, and
+//              the elimination of every 16-cell row segment and 16-cell column
 //              segment down to its first and last unknowns (partition
 //              method); writes the eliminated interior values in place and
 //              two reduced equations per segment.
@@ -18,13 +21,11 @@
 //   k_expand   per tile: back substitution of every segment from its solved
 //              end values, P = P^n + dP, Q = Q^n + dQ, shoreline fix (and the
 //              sponge after the last pass).
+// k_ghosts precomputes the wave-maker ghost values of one time level.
 #pragma once
 #include "ws_device.hpp"
 
 namespace ws {
-
-constexpr int HX = TX + 4, HY = TY + 4;  // state halo tile (2 ghost cells per side)
-constexpr int CX = TX + 5, CY = TY + 5;  // corner tile of the halo
 
 struct StencilArgs {
     Dom d;
@@ -34,7 +35,6 @@ struct StencilArgs {
     const float *E1, *F1, *G1, *Fs1, *Gs1;  // level n-1
     const float *E2, *F2, *G2, *Fs2, *Gs2;  // level n-2
     float *Se, *SU, *SV;               // corrector bases (eta, U* and V* increments)
-    double t;                          // time of the ghost values
     float dt, x0, x1, x2;              // step, F* extrapolation weights
     int kind;                          // 0 Euler predictor, 1 AB3 predictor, 2 AM4 corrector
     int write_S;
@@ -44,167 +44,183 @@ __device__ __forceinline__ float dcell4(float a, float b, float c, float d) {
     return fmaxf(0.25f * ((a + b) + (c + d)), 0.f);
 }
 
-__global__ __launch_bounds__(NT) void k_stencil(StencilArgs A) {
-    __shared__ float se[HY][HX], sp[HY][HX], sq[HY][HX];
-    __shared__ float sD[CY][CX];
-    __shared__ float fx[3][TY][TX + 1];
-    __shared__ float fy[3][TY + 1][TX];
+// Ghost values of every wave-maker side at time t (eqs. 25-28 per component).
+__global__ void k_ghosts(Dom d, float *gh, double t) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int pos = k % d.gl, layer = (k / d.gl) % 2, side = k / (2 * d.gl);
+    if (side >= 4 || d.side[side].type != BC_WAVES) return;
+    int i, j;
+    if (side < 2) {
+        i = side == 0 ? -1 - layer : d.nx + layer;
+        j = pos - 2;
+    } else {
+        j = side == 2 ? -1 - layer : d.ny + layer;
+        i = pos - 2;
+    }
+    float e, p, q;
+    wave_eval(d.side[side], (i + 0.5) * (double)d.dx, (j + 0.5) * (double)d.dy, t, e, p, q);
+    float *o = gh + ghost_index(d, side, layer, pos);
+    o[0] = e;
+    o[1] = p;
+    o[2] = q;
+}
+
+__global__ __launch_bounds__(64 * SWG) void k_stencil(StencilArgs A) {
     const Dom &d = A.d;
-    const int tid = threadIdx.x;
-    const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+    const int lane = threadIdx.x & 63;
+    const int strip = blockIdx.x * SWG + (threadIdx.x >> 6);
+    const int c0 = strip * SO - 1;  // column of lane 0; lanes 1..62 are output columns
+    if (c0 + 1 >= d.nx) return;     // whole wave past the domain
+    const int col = c0 + lane;
+    const int hcol = lane == 0 ? c0 - 1 : c0 + 64;  // halo column held by lanes 0 and 63
+    const bool halo_lane = lane == 0 || lane == 63;
+    const int j0 = blockIdx.y * SY;
     const float th = d.theta, g = d.g, eps = d.eps;
-
-    for (int k = tid; k < HX * HY; k += NT) {
-        int lx = k % HX, ly = k / HX;
-        float e, p, q;
-        load_cell(d, A.ein, A.pin, A.qin, i0 + lx - 2, j0 + ly - 2, A.t, e, p, q);
-        se[ly][lx] = e;
-        sp[ly][lx] = p;
-        sq[ly][lx] = q;
-    }
-    for (int k = tid; k < CX * CY; k += NT) {
-        int lx = k % CX, ly = k / CX;
-        sD[ly][lx] = corner_D(d, i0 + lx - 2, j0 + ly - 2);
-    }
-    __syncthreads();
-
-    // x-faces: face fi lies between local cells fi+1 and fi+2 of row fj+2
-    for (int k = tid; k < (TX + 1) * TY; k += NT) {
-        int fi = k % (TX + 1), fj = k / (TX + 1);
-        int ly = fj + 2, a = fi + 1, b = fi + 2;
-        float Dwa = 0.5f * (sD[ly][a] + sD[ly + 1][a]);
-        float Df = 0.5f * (sD[ly][b] + sD[ly + 1][b]);
-        float Deb = 0.5f * (sD[ly][b + 1] + sD[ly + 1][b + 1]);
-        F3 lo, hiL, loR, hi;
-        reconstruct(se[ly][a - 1], se[ly][a], se[ly][a + 1], sp[ly][a - 1], sp[ly][a], sp[ly][a + 1],
-                    sq[ly][a - 1], sq[ly][a], sq[ly][a + 1], Dwa, Df, th, lo, hiL);
-        reconstruct(se[ly][b - 1], se[ly][b], se[ly][b + 1], sp[ly][b - 1], sp[ly][b], sp[ly][b + 1],
-                    sq[ly][b - 1], sq[ly][b], sq[ly][b + 1], Df, Deb, th, loR, hi);
-        float H0, H1, H2;
-        cu_flux(g, eps, Df, hiL, loR, H0, H1, H2);
-        fx[0][fj][fi] = H0;
-        fx[1][fj][fi] = H1;
-        fx[2][fj][fi] = H2;
-    }
-    // y-faces: face fj lies between local rows fj+1 and fj+2 of column fi+2;
-    // the normal discharge is Q
-    for (int k = tid; k < TX * (TY + 1); k += NT) {
-        int fi = k % TX, fj = k / TX;
-        int lx = fi + 2, a = fj + 1, b = fj + 2;
-        float Dsa = 0.5f * (sD[a][lx] + sD[a][lx + 1]);
-        float Df = 0.5f * (sD[b][lx] + sD[b][lx + 1]);
-        float Dnb = 0.5f * (sD[b + 1][lx] + sD[b + 1][lx + 1]);
-        F3 lo, hiL, loR, hi;
-        reconstruct(se[a - 1][lx], se[a][lx], se[a + 1][lx], sq[a - 1][lx], sq[a][lx], sq[a + 1][lx],
-                    sp[a - 1][lx], sp[a][lx], sp[a + 1][lx], Dsa, Df, th, lo, hiL);
-        reconstruct(se[b - 1][lx], se[b][lx], se[b + 1][lx], sq[b - 1][lx], sq[b][lx], sq[b + 1][lx],
-                    sp[b - 1][lx], sp[b][lx], sp[b + 1][lx], Df, Dnb, th, loR, hi);
-        float H0, H1, H2;
-        cu_flux(g, eps, Df, hiL, loR, H0, H1, H2);
-        fy[0][fj][fi] = H0;
-        fy[1][fj][fi] = H2;  // x-momentum (tangential)
-        fy[2][fj][fi] = H1;  // y-momentum (normal)
-    }
-    __syncthreads();
-
     const float rdx = d.rdx, rdy = d.rdy, Bd = d.Bd, B3 = d.Bd + 1.f / 3.f;
-    const int cx = tid % TX;
-    for (int cy = tid / TX; cy < TY; cy += NT / TX) {
-        const int i = i0 + cx, j = j0 + cy;
-        if (i >= d.nx || j >= d.ny) continue;
-        const int lx = cx + 2, ly = cy + 2;
-        const float c00 = sD[ly][lx], c10 = sD[ly][lx + 1], c01 = sD[ly + 1][lx], c11 = sD[ly + 1][lx + 1];
-        const float Dc = 0.25f * ((c00 + c10) + (c01 + c11));
-        const float Dw = 0.5f * (c00 + c01), De = 0.5f * (c10 + c11);
-        const float Ds = 0.5f * (c00 + c10), Dn = 0.5f * (c01 + c11);
-        const float e0 = se[ly][lx], p0 = sp[ly][lx], q0 = sq[ly][lx];
 
-        float E = -(fx[0][cy][cx + 1] - fx[0][cy][cx]) * rdx - (fy[0][cy + 1][cx] - fy[0][cy][cx]) * rdy;
-        float F = -(fx[1][cy][cx + 1] - fx[1][cy][cx]) * rdx - (fy[1][cy + 1][cx] - fy[1][cy][cx]) * rdy +
-                  g * (De - Dw) * rdx * e0;
-        float G = -(fx[2][cy][cx + 1] - fx[2][cy][cx]) * rdx - (fy[2][cy + 1][cx] - fy[2][cy][cx]) * rdy +
-                  g * (Dn - Ds) * rdy * e0;
-        float Fs = 0.f, Gs = 0.f;
+    // sliding windows (row index relative to the row r loaded this iteration)
+    float e0 = 0.f, e1 = 0.f, e2 = 0.f, e3 = 0.f, e4 = 0.f;  // eta rows r-4 .. r
+    float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;            // P rows r-3 .. r
+    float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;            // Q rows r-3 .. r
+    float he0 = 0.f, he1 = 0.f, he2 = 0.f, hp0 = 0.f, hp1 = 0.f, hp2 = 0.f;  // halo rows r-2 .. r
+    float hq0 = 0.f, hq1 = 0.f, hq2 = 0.f;
+    float Dl0 = 0.f, Dl1 = 0.f, Dl2 = 0.f, Dl3 = 0.f;        // corner depth at col, rows r-3 .. r
+    float Dr0 = 0.f, Dr1 = 0.f, Dr2 = 0.f, Dr3 = 0.f;        // corner depth at col+1
+    F3 hiy_prev = {0.f, 0.f, 0.f};                           // y-reconstruction, north side of row r-2
+    float Hs0 = 0.f, Hs1 = 0.f, Hs2 = 0.f;                   // flux through the south face of row r-2
 
-        const float dep = fmaxf(Dc, 0.f);
-        const float dxm = dcell4(sD[ly][lx - 1], sD[ly][lx], sD[ly + 1][lx - 1], sD[ly + 1][lx]);
-        const float dxp = dcell4(sD[ly][lx + 1], sD[ly][lx + 2], sD[ly + 1][lx + 1], sD[ly + 1][lx + 2]);
-        const float dym = dcell4(sD[ly - 1][lx], sD[ly - 1][lx + 1], sD[ly][lx], sD[ly][lx + 1]);
-        const float dyp = dcell4(sD[ly + 1][lx], sD[ly + 1][lx + 1], sD[ly + 2][lx], sD[ly + 2][lx + 1]);
-        const float ddx = (dxp - dxm) * 0.5f * rdx, ddy = (dyp - dym) * 0.5f * rdy;
+    for (int it = 0; it < SY + 4; ++it) {
+        const int r = j0 - 2 + it;
+        e0 = e1; e1 = e2; e2 = e3; e3 = e4;
+        p0 = p1; p1 = p2; p2 = p3;
+        q0 = q1; q1 = q2; q2 = q3;
+        he0 = he1; he1 = he2; hp0 = hp1; hp1 = hp2; hq0 = hq1; hq1 = hq2;
+        Dl0 = Dl1; Dl1 = Dl2; Dl2 = Dl3;
+        Dr0 = Dr1; Dr1 = Dr2; Dr2 = Dr3;
+        load_cell(d, A.ein, A.pin, A.qin, col, r, e4, p3, q3);
+        if (halo_lane) load_cell(d, A.ein, A.pin, A.qin, hcol, r, he2, hp2, hq2);
+        Dl3 = corner_D(d, col, r);
+        Dr3 = corner_D(d, col + 1, r);
+        if (it < 2) continue;
 
-        if (d.model == BSNQ) {
-            const float em1 = se[ly][lx - 1], ep1 = se[ly][lx + 1], em2 = se[ly][lx - 2], ep2 = se[ly][lx + 2];
-            const float fm1 = se[ly - 1][lx], fp1 = se[ly + 1][lx], fm2 = se[ly - 2][lx], fp2 = se[ly + 2][lx];
-            const float epp = se[ly + 1][lx + 1], epm = se[ly - 1][lx + 1];
-            const float emp = se[ly + 1][lx - 1], emm = se[ly - 1][lx - 1];
-            const float exx = (ep1 - 2.f * e0 + em1) * rdx * rdx;
-            const float eyy = (fp1 - 2.f * e0 + fm1) * rdy * rdy;
-            const float exy = (epp - epm - emp + emm) * 0.25f * rdx * rdy;
-            const float exxx = (ep2 - 2.f * ep1 + 2.f * em1 - em2) * 0.5f * rdx * rdx * rdx;
-            const float eyyy = (fp2 - 2.f * fp1 + 2.f * fm1 - fm2) * 0.5f * rdy * rdy * rdy;
-            const float exyy = ((epp - 2.f * ep1 + epm) - (emp - 2.f * em1 + emm)) * 0.5f * rdx * rdy * rdy;
-            const float exxy = ((epp - 2.f * fp1 + emp) - (epm - 2.f * fm1 + emm)) * 0.5f * rdx * rdx * rdy;
-            const float gb = Bd * g * dep * dep;
-            F += gb * (dep * (exxx + exyy) + ddx * (2.f * exx + eyy) + ddy * exy);
-            G += gb * (dep * (eyyy + exxy) + ddy * (2.f * eyy + exx) + ddx * exy);
-            const float Px = (sp[ly][lx + 1] - sp[ly][lx - 1]) * 0.5f * rdx;
-            const float Py = (sp[ly + 1][lx] - sp[ly - 1][lx]) * 0.5f * rdy;
-            const float Pxy = (sp[ly + 1][lx + 1] - sp[ly - 1][lx + 1] - sp[ly + 1][lx - 1] + sp[ly - 1][lx - 1]) *
-                              0.25f * rdx * rdy;
-            const float Qx = (sq[ly][lx + 1] - sq[ly][lx - 1]) * 0.5f * rdx;
-            const float Qy = (sq[ly + 1][lx] - sq[ly - 1][lx]) * 0.5f * rdy;
-            const float Qxy = (sq[ly + 1][lx + 1] - sq[ly - 1][lx + 1] - sq[ly + 1][lx - 1] + sq[ly - 1][lx - 1]) *
-                              0.25f * rdx * rdy;
-            Fs = dep * (ddx * Qy + ddy * Qx) * (1.f / 6.f) + B3 * dep * dep * Qxy;
-            Gs = dep * (ddy * Px + ddx * Py) * (1.f / 6.f) + B3 * dep * dep * Pxy;
-        }
-        if (d.friction != FRIC_NONE) {
-            const float h = fmaxf(e0 + Dc, 0.f), h2 = h * h, h4 = h2 * h2;
-            const float inv_h = 1.41421356237f * h * rsqrtf(h4 + fmaxf(h4, eps));
-            float fc = d.fcoef;
-            if (d.friction == FRIC_MANNING) fc = g * d.fcoef * d.fcoef * cbrtf(inv_h);
-            const float k = fc * sqrtf(p0 * p0 + q0 * q0) * inv_h * inv_h;
-            F -= k * p0;
-            G -= k * q0;
-        }
+        // y-reconstruction of row r-1 (normal discharge Q) and the flux
+        // through its south face (between rows r-2 and r-1)
+        const float Dys = 0.5f * (Dl2 + Dr2), Dyn = 0.5f * (Dl3 + Dr3);
+        F3 loy, hiy;
+        reconstruct(e2, e3, e4, q1, q2, q3, p1, p2, p3, Dys, Dyn, th, loy, hiy);
+        float Hn0 = 0.f, Hn1 = 0.f, Hn2 = 0.f;  // (mass, y-momentum, x-momentum)
+        if (it >= 3) cu_flux(g, eps, Dys, hiy_prev, loy, Hn0, Hn1, Hn2);
 
-        const size_t o = (size_t)j * d.pitch + i;
-        float en, U = 0.f, V = 0.f;   // increments of U*, V* over the step
-        if (A.kind != 2) {
-            A.hE[o] = E;
-            A.hF[o] = F;
-            A.hG[o] = G;
-            A.hFs[o] = Fs;
-            A.hGs[o] = Gs;
-        }
-        const float dt = A.dt;
-        if (A.kind == 0) {
-            en = e0 + dt * E;
-            U += dt * F;
-            V += dt * G;
-        } else if (A.kind == 1) {
-            const float e1 = A.E1[o], e2 = A.E2[o], f1 = A.F1[o], f2 = A.F2[o], g1 = A.G1[o], g2 = A.G2[o];
-            const float fs1 = A.Fs1[o], gs1 = A.Gs1[o];
-            const float fs2 = A.x2 != 0.f ? A.Fs2[o] : 0.f, gs2 = A.x2 != 0.f ? A.Gs2[o] : 0.f;
-            const float c12 = dt * (1.f / 12.f), c24 = dt * (1.f / 24.f);
-            if (A.write_S) {
-                A.Se[o] = e0 + c24 * (19.f * E - 5.f * e1 + e2);
-                A.SU[o] = U + c24 * (19.f * F - 5.f * f1 + f2) - Fs;
-                A.SV[o] = V + c24 * (19.f * G - 5.f * g1 + g2) - Gs;
+        if (it >= 4) {  // update row u = r - 2
+            const int u = r - 2;
+            const bool out = lane >= 1 && lane <= 62 && col < d.nx && u < d.ny;
+            const size_t o = (size_t)u * d.pitch + col;
+            float E1v = 0.f, F1v = 0.f, G1v = 0.f, Fs1v = 0.f, Gs1v = 0.f, E2v = 0.f, F2v = 0.f, G2v = 0.f;
+            float Fs2v = 0.f, Gs2v = 0.f, Sev = 0.f, SUv = 0.f, SVv = 0.f;
+            if (out) {
+                if (A.kind == 1) {
+                    E1v = A.E1[o]; F1v = A.F1[o]; G1v = A.G1[o]; Fs1v = A.Fs1[o]; Gs1v = A.Gs1[o];
+                    E2v = A.E2[o]; F2v = A.F2[o]; G2v = A.G2[o];
+                    if (A.x2 != 0.f) { Fs2v = A.Fs2[o]; Gs2v = A.Gs2[o]; }
+                } else if (A.kind == 2) {
+                    Sev = A.Se[o]; SUv = A.SU[o]; SVv = A.SV[o];
+                }
             }
-            en = e0 + c12 * (23.f * E - 16.f * e1 + 5.f * e2);
-            U = U + c12 * (23.f * F - 16.f * f1 + 5.f * f2) + (A.x0 * Fs + A.x1 * fs1 + A.x2 * fs2);
-            V = V + c12 * (23.f * G - 16.f * g1 + 5.f * g2) + (A.x0 * Gs + A.x1 * gs1 + A.x2 * gs2);
-        } else {
-            const float c9 = dt * (9.f / 24.f);
-            en = A.Se[o] + c9 * E;
-            U = A.SU[o] + c9 * F + Fs;
-            V = A.SV[o] + c9 * G + Gs;
+            // cell and face still-water depths
+            const float Dc = 0.25f * ((Dl1 + Dr1) + (Dl2 + Dr2));
+            const float Dw = 0.5f * (Dl1 + Dl2), De = 0.5f * (Dr1 + Dr2);
+            const float Ds = 0.5f * (Dl1 + Dr1), Dn = Dys;
+            // x-reconstruction of row u (normal discharge P); lanes 0 and 63
+            // take their outer neighbour from the halo columns
+            const float em = shr1(e2, he0), ep = shl1(e2, he0);
+            const float pm = shr1(p1, hp0), pp = shl1(p1, hp0);
+            const float qm = shr1(q1, hq0), qp = shl1(q1, hq0);
+            F3 lox, hix;
+            reconstruct(em, e2, ep, pm, p1, pp, qm, q1, qp, Dw, De, th, lox, hix);
+            const F3 hil = {shr1(hix.e, hix.e), shr1(hix.n, hix.n), shr1(hix.t, hix.t)};
+            float Hw0, Hw1, Hw2;  // west face: (mass, x-momentum, y-momentum)
+            cu_flux(g, eps, Dw, hil, lox, Hw0, Hw1, Hw2);
+            const float He0 = shl1(Hw0, Hw0), He1 = shl1(Hw1, Hw1), He2 = shl1(Hw2, Hw2);
+
+            float E = -(He0 - Hw0) * rdx - (Hn0 - Hs0) * rdy;
+            float F = -(He1 - Hw1) * rdx - (Hn2 - Hs2) * rdy + g * (De - Dw) * rdx * e2;
+            float G = -(He2 - Hw2) * rdx - (Hn1 - Hs1) * rdy + g * (Dn - Ds) * rdy * e2;
+            float Fs = 0.f, Gs = 0.f;
+
+            const float dep = fmaxf(Dc, 0.f);
+            const float dxm = shr1(dep, dep), dxp = shl1(dep, dep);
+            const float dym = dcell4(Dl0, Dr0, Dl1, Dr1), dyp = dcell4(Dl2, Dr2, Dl3, Dr3);
+            const float ddx = (dxp - dxm) * 0.5f * rdx, ddy = (dyp - dym) * 0.5f * rdy;
+
+            if (d.model == BSNQ) {
+                const float em2 = shr1(em, em), ep2 = shl1(ep, ep);
+                const float epp = shl1(e3, e3), epm = shl1(e1, e1);
+                const float emp = shr1(e3, e3), emm = shr1(e1, e1);
+                const float exx = (ep - 2.f * e2 + em) * rdx * rdx;
+                const float eyy = (e3 - 2.f * e2 + e1) * rdy * rdy;
+                const float exy = (epp - epm - emp + emm) * 0.25f * rdx * rdy;
+                const float exxx = (ep2 - 2.f * ep + 2.f * em - em2) * 0.5f * rdx * rdx * rdx;
+                const float eyyy = (e4 - 2.f * e3 + 2.f * e1 - e0) * 0.5f * rdy * rdy * rdy;
+                const float exyy = ((epp - 2.f * ep + epm) - (emp - 2.f * em + emm)) * 0.5f * rdx * rdy * rdy;
+                const float exxy = ((epp - 2.f * e3 + emp) - (epm - 2.f * e1 + emm)) * 0.5f * rdx * rdx * rdy;
+                const float gb = Bd * g * dep * dep;
+                F += gb * (dep * (exxx + exyy) + ddx * (2.f * exx + eyy) + ddy * exy);
+                G += gb * (dep * (eyyy + exxy) + ddy * (2.f * eyy + exx) + ddx * exy);
+                const float Px = (pp - pm) * 0.5f * rdx, Py = (p2 - p0) * 0.5f * rdy;
+                const float Pxy = (shl1(p2, p2) - shl1(p0, p0) - shr1(p2, p2) + shr1(p0, p0)) * 0.25f * rdx * rdy;
+                const float Qx = (qp - qm) * 0.5f * rdx, Qy = (q2 - q0) * 0.5f * rdy;
+                const float Qxy = (shl1(q2, q2) - shl1(q0, q0) - shr1(q2, q2) + shr1(q0, q0)) * 0.25f * rdx * rdy;
+                Fs = dep * (ddx * Qy + ddy * Qx) * (1.f / 6.f) + B3 * dep * dep * Qxy;
+                Gs = dep * (ddy * Px + ddx * Py) * (1.f / 6.f) + B3 * dep * dep * Pxy;
+            }
+            if (d.friction != FRIC_NONE) {
+                const float h = fmaxf(e2 + Dc, 0.f), h2 = h * h, h4 = h2 * h2;
+                const float inv_h = 1.41421356237f * h * frsq(h4 + fmaxf(h4, eps));
+                float fc = d.fcoef;
+                if (d.friction == FRIC_MANNING) fc = g * d.fcoef * d.fcoef * cbrtf(inv_h);
+                const float k = fc * fsqrt(p1 * p1 + q1 * q1) * inv_h * inv_h;
+                F -= k * p1;
+                G -= k * q1;
+            }
+            if (out) {
+                const float dt = A.dt;
+                float en, U, V;  // new surface, increments of U*, V* over the step
+                if (A.kind == 0) {
+                    en = e2 + dt * E;
+                    U = dt * F;
+                    V = dt * G;
+                } else if (A.kind == 1) {
+                    const float c12 = dt * (1.f / 12.f), c24 = dt * (1.f / 24.f);
+                    if (A.write_S) {
+                        A.Se[o] = e2 + c24 * (19.f * E - 5.f * E1v + E2v);
+                        A.SU[o] = c24 * (19.f * F - 5.f * F1v + F2v) - Fs;
+                        A.SV[o] = c24 * (19.f * G - 5.f * G1v + G2v) - Gs;
+                    }
+                    en = e2 + c12 * (23.f * E - 16.f * E1v + 5.f * E2v);
+                    U = c12 * (23.f * F - 16.f * F1v + 5.f * F2v) + (A.x0 * Fs + A.x1 * Fs1v + A.x2 * Fs2v);
+                    V = c12 * (23.f * G - 16.f * G1v + 5.f * G2v) + (A.x0 * Gs + A.x1 * Gs1v + A.x2 * Gs2v);
+                } else {
+                    const float c9 = dt * (9.f / 24.f);
+                    en = Sev + c9 * E;
+                    U = SUv + c9 * F + Fs;
+                    V = SVv + c9 * G + Gs;
+                }
+                if (A.kind != 2) {
+                    A.hE[o] = E;
+                    A.hF[o] = F;
+                    A.hG[o] = G;
+                    A.hFs[o] = Fs;
+                    A.hGs[o] = Gs;
+                }
+                A.eout[o] = fmaxf(en, -Dc);
+                A.rx[o] = U;
+                A.ry[o] = V;
+            }
         }
-        A.eout[o] = fmaxf(en, -Dc);
-        A.rx[o] = U;
-        A.ry[o] = V;
+        hiy_prev = hiy;
+        Hs0 = Hn0;
+        Hs1 = Hn1;
+        Hs2 = Hn2;
     }
 }
 
@@ -216,145 +232,153 @@ struct SolveArgs {
     float *solx, *soly;        // reduced solutions
     float *eta, *pout, *qout;  // new surface (read; sponge writes it), new P, Q
     const float *pbase, *qbase;  // P^n, Q^n of the step
+    const float *gh0, *gh1;    // wave-maker ghosts at t^n and t^{n+1}
     int *health;
-    double t0, t1;             // wave-maker ghosts of the boundary rows: t^n and t^{n+1}
     int sponge;
 };
 
+constexpr int TXP = TX + 1;  // padded LDS row: segment k of row r starts at bank r + 16k
+
 struct SolveTile {
-    float rx[TY][TX], ry[TY][TX];
-    float D[TY + 3][TX + 3];   // corners of cells -1..TX, -1..TY
-    float xa[TY][TX], xb[TY][TX], xc[TY][TX];
-    float ya[TY][TX], yb[TY][TX], yc[TY][TX];
+    float rx[TY][TXP], ry[TY][TXP];   // right-hand sides / solution of the tile
+    float cz[TY + 3][TX + 3];         // corner depths, corners -1 .. TX+1, -1 .. TY+1
+    float dc[TY + 2][TX + 2];         // cell still-water depth D (unclamped), cells -1..TX, -1..TY
 };
 
-__device__ __forceinline__ float tile_dcell(const SolveTile &s, int cx, int cy) {
-    return dcell4(s.D[cy + 1][cx + 1], s.D[cy + 1][cx + 2], s.D[cy + 2][cx + 1], s.D[cy + 2][cx + 2]);
+// Discharge change of a wave-maker ghost over the step (first ghost layer).
+__device__ __forceinline__ float ghost_change(const SolveArgs &A, int side, int pos, int comp) {
+    const size_t k = ghost_index(A.d, side, 0, pos) + comp;
+    return A.gh1[k] - A.gh0[k];
 }
 
-// Load the tile's corners and fill the row (x) and column (y) coefficients of
-// eq. 23 for every cell, folding the boundary rows: behind a wall the ghost
-// is the odd mirror of the first unknown (diagonal -= off-diagonal), behind a
-// wave maker it is the maker's discharge, known, so its change over the step
-// moves to the right-hand side of the delta-form system (when adjust_rhs).
-// Padding cells become identity rows with zero right-hand side.
-// Change of a wave maker's ghost discharge (P if comp == 0, else Q) from t^n
-// to t^{n+1} at (x, y).
-__device__ inline float ghost_change(const SideDev &sd, double x, double y, const SolveArgs &A, int comp) {
-    float e0, p0, q0, e1, p1, q1;
-    wave_eval(sd, x, y, A.t0, e0, p0, q0);
-    wave_eval(sd, x, y, A.t1, e1, p1, q1);
-    return comp == 0 ? p1 - p0 : q1 - q0;
+// Stage the tile's corner and cell depths in LDS.
+__device__ void load_depths(const Dom &d, SolveTile &s, int i0, int j0) {
+    for (int k = threadIdx.x; k < (TX + 3) * (TY + 3); k += NT) {
+        const int lx = k % (TX + 3), ly = k / (TX + 3);
+        s.cz[ly][lx] = corner_D(d, i0 + lx - 1, j0 + ly - 1);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < (TX + 2) * (TY + 2); k += NT) {
+        const int lx = k % (TX + 2), ly = k / (TX + 2);
+        s.dc[ly][lx] = 0.25f * ((s.cz[ly][lx] + s.cz[ly][lx + 1]) + (s.cz[ly + 1][lx] + s.cz[ly + 1][lx + 1]));
+    }
+    __syncthreads();
 }
 
-__device__ void fill_coefs(const SolveArgs &A, SolveTile &s, int i0, int j0, bool adjust_rhs) {
+// Coefficients of eq. 23 of one segment of M cells, in registers.  dir 0:
+// cells (x0 + k, y) of a tile row; dir 1: cells (x, y0 + k) of a tile column
+// (tile-local indices).  Boundary rows are folded: behind a wall the ghost is
+// the odd mirror of the first unknown (diagonal -= off-diagonal); behind a
+// wave maker it is the maker's known discharge, whose change over the step
+// moves to the right-hand side of the delta-form system (r, when given).
+// Padding cells are identity rows with zero right-hand side.
+template <int M>
+__device__ __forceinline__ void seg_coefs(const SolveArgs &A, const SolveTile &s, int i0, int j0, int dir,
+                                          int x0, int y0, float (&a)[M], float (&b)[M], float (&c)[M],
+                                          float *r, int st) {
     const Dom &d = A.d;
-    const int tid = threadIdx.x;
-    for (int k = tid; k < (TX + 3) * (TY + 3); k += NT) {
-        int lx = k % (TX + 3), ly = k / (TX + 3);
-        s.D[ly][lx] = corner_D(d, i0 + lx - 1, j0 + ly - 1);
-    }
-    __syncthreads();
-    for (int k = tid; k < TX * TY; k += NT) {
-        const int cx = k % TX, cy = k / TX, i = i0 + cx, j = j0 + cy;
-        float a = 0.f, b = 1.f, c = 0.f, a2 = 0.f, b2 = 1.f, c2 = 0.f;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const int cx = dir == 0 ? x0 + k : x0, cy = dir == 0 ? y0 : y0 + k;
+        const int i = i0 + cx, j = j0 + cy;
+        float aa = 0.f, bb = 1.f, cc = 0.f;
         if (i < d.nx && j < d.ny) {
-            const float dep = tile_dcell(s, cx, cy);
-            const float ddx = (tile_dcell(s, cx + 1, cy) - tile_dcell(s, cx - 1, cy)) * 0.5f * d.rdx;
-            const float ddy = (tile_dcell(s, cx, cy + 1) - tile_dcell(s, cx, cy - 1)) * 0.5f * d.rdy;
-            tri_coef(d, dep, ddx, d.rdx, a, b, c);
-            tri_coef(d, dep, ddy, d.rdy, a2, b2, c2);
-            if (i == 0) {
-                if (is_wall(d, 0)) b -= a;
-                else if (adjust_rhs)
-                    s.rx[cy][cx] -= a * ghost_change(d.side[0], -0.5 * d.dx, (j + 0.5) * (double)d.dy, A, 0);
-                a = 0.f;
+            const float dep = fmaxf(s.dc[cy + 1][cx + 1], 0.f);
+            if (dir == 0) {
+                const float dd = (fmaxf(s.dc[cy + 1][cx + 2], 0.f) - fmaxf(s.dc[cy + 1][cx], 0.f)) * 0.5f * d.rdx;
+                tri_coef(d, dep, dd, d.rdx, aa, bb, cc);
+                if (i == 0) {
+                    if (is_wall(d, 0)) bb -= aa;
+                    else if (r) r[k * st] -= aa * ghost_change(A, 0, j + 2, 1);
+                    aa = 0.f;
+                }
+                if (i == d.nx - 1) {
+                    if (is_wall(d, 1)) bb -= cc;
+                    else if (r) r[k * st] -= cc * ghost_change(A, 1, j + 2, 1);
+                    cc = 0.f;
+                }
+            } else {
+                const float dd = (fmaxf(s.dc[cy + 2][cx + 1], 0.f) - fmaxf(s.dc[cy][cx + 1], 0.f)) * 0.5f * d.rdy;
+                tri_coef(d, dep, dd, d.rdy, aa, bb, cc);
+                if (j == 0) {
+                    if (is_wall(d, 2)) bb -= aa;
+                    else if (r) r[k * st] -= aa * ghost_change(A, 2, i + 2, 2);
+                    aa = 0.f;
+                }
+                if (j == d.ny - 1) {
+                    if (is_wall(d, 3)) bb -= cc;
+                    else if (r) r[k * st] -= cc * ghost_change(A, 3, i + 2, 2);
+                    cc = 0.f;
+                }
             }
-            if (i == d.nx - 1) {
-                if (is_wall(d, 1)) b -= c;
-                else if (adjust_rhs)
-                    s.rx[cy][cx] -= c * ghost_change(d.side[1], (d.nx + 0.5) * (double)d.dx, (j + 0.5) * (double)d.dy, A, 0);
-                c = 0.f;
-            }
-            if (j == 0) {
-                if (is_wall(d, 2)) b2 -= a2;
-                else if (adjust_rhs)
-                    s.ry[cy][cx] -= a2 * ghost_change(d.side[2], (i + 0.5) * (double)d.dx, -0.5 * d.dy, A, 1);
-                a2 = 0.f;
-            }
-            if (j == d.ny - 1) {
-                if (is_wall(d, 3)) b2 -= c2;
-                else if (adjust_rhs)
-                    s.ry[cy][cx] -= c2 * ghost_change(d.side[3], (i + 0.5) * (double)d.dx, (d.ny + 0.5) * (double)d.dy, A, 1);
-                c2 = 0.f;
-            }
-        } else if (adjust_rhs) {
-            s.rx[cy][cx] = 0.f;
-            s.ry[cy][cx] = 0.f;
+        } else if (r) {
+            r[k * st] = 0.f;
         }
-        s.xa[cy][cx] = a;
-        s.xb[cy][cx] = b;
-        s.xc[cy][cx] = c;
-        s.ya[cy][cx] = a2;
-        s.yb[cy][cx] = b2;
-        s.yc[cy][cx] = c2;
+        a[k] = aa;
+        b[k] = bb;
+        c[k] = cc;
     }
-    __syncthreads();
 }
 
-// Partition-method elimination of one segment of M unknowns (stride st in
-// LDS): afterwards every interior row k reads  a_k x_0 + b_k x_k + c_k x_{M-1}
-// = r_k (r overwritten), and the first and last rows are returned as reduced
+// Partition-method elimination of one segment of M unknowns: afterwards every
+// interior row k reads  a_k x_0 + b_k x_k + c_k x_{M-1} = r_k (r overwritten,
+// stride st in LDS), and the first and last rows are returned as reduced
 // equations coupling (x_{-1}, x_0, x_{M-1}) and (x_0, x_{M-1}, x_M).
 template <int M>
-__device__ void seg_eliminate(float *r, float *a, float *b, const float *c, int st, float4 &first,
-                              float4 &last) {
+__device__ __forceinline__ void seg_eliminate(float *r, int st, float (&a)[M], float (&b)[M],
+                                              const float (&c)[M], float4 &first, float4 &last) {
+#pragma unroll
     for (int k = 2; k <= M - 2; ++k) {  // forward: eliminate x_{k-1} in favour of x_0
-        const float f = a[k * st] / b[(k - 1) * st];
-        a[k * st] = -f * a[(k - 1) * st];
-        b[k * st] = b[k * st] - f * c[(k - 1) * st];
+        const float f = a[k] * frcp(b[k - 1]);
+        a[k] = -f * a[k - 1];
+        b[k] = b[k] - f * c[k - 1];
         r[k * st] = r[k * st] - f * r[(k - 1) * st];
     }
     {
-        const float f = a[(M - 1) * st] / b[(M - 2) * st];
-        last = make_float4(-f * a[(M - 2) * st], b[(M - 1) * st] - f * c[(M - 2) * st],
-                           c[(M - 1) * st], r[(M - 1) * st] - f * r[(M - 2) * st]);
+        const float f = a[M - 1] * frcp(b[M - 2]);
+        last = make_float4(-f * a[M - 2], b[M - 1] - f * c[M - 2], c[M - 1], r[(M - 1) * st] - f * r[(M - 2) * st]);
     }
-    float ah = a[(M - 2) * st], bh = b[(M - 2) * st], ch = c[(M - 2) * st], rh = r[(M - 2) * st];
+    float ah = a[M - 2], bh = b[M - 2], ch = c[M - 2], rh = r[(M - 2) * st];
+#pragma unroll
     for (int k = M - 3; k >= 1; --k) {  // backward: eliminate x_{k+1} in favour of x_{M-1}
-        const float f = c[k * st] / bh;
-        ah = a[k * st] - f * ah;
-        bh = b[k * st];
+        const float f = c[k] * frcp(bh);
+        ah = a[k] - f * ah;
+        bh = b[k];
         ch = -f * ch;
         rh = r[k * st] - f * rh;
         r[k * st] = rh;
     }
-    const float f = c[0] / bh;
+    const float f = c[0] * frcp(bh);
     first = make_float4(a[0], b[0] - f * ah, -f * ch, r[0] - f * rh);
 }
 
 // Back substitution of one segment from its solved end values x0, xl; r holds
 // the eliminated interior values on entry and the solution on exit.
 template <int M>
-__device__ void seg_expand(float *r, float *a, float *b, const float *c, int st, float x0, float xl) {
+__device__ __forceinline__ void seg_expand(float *r, int st, float (&a)[M], float (&b)[M],
+                                           const float (&c)[M], float x0, float xl) {
+#pragma unroll
     for (int k = 2; k <= M - 2; ++k) {
-        const float f = a[k * st] / b[(k - 1) * st];
-        a[k * st] = -f * a[(k - 1) * st];
-        b[k * st] = b[k * st] - f * c[(k - 1) * st];
+        const float f = a[k] * frcp(b[k - 1]);
+        a[k] = -f * a[k - 1];
+        b[k] = b[k] - f * c[k - 1];
     }
-    float ah = a[(M - 2) * st], bh = b[(M - 2) * st], ch = c[(M - 2) * st];
-    r[(M - 2) * st] = (r[(M - 2) * st] - ah * x0 - ch * xl) / bh;
+    float ah = a[M - 2], bh = b[M - 2], ch = c[M - 2];
+    r[(M - 2) * st] = (r[(M - 2) * st] - ah * x0 - ch * xl) * frcp(bh);
+#pragma unroll
     for (int k = M - 3; k >= 1; --k) {
-        const float f = c[k * st] / bh;
-        ah = a[k * st] - f * ah;
-        bh = b[k * st];
+        const float f = c[k] * frcp(bh);
+        ah = a[k] - f * ah;
+        bh = b[k];
         ch = -f * ch;
-        r[k * st] = (r[k * st] - ah * x0 - ch * xl) / bh;
+        r[k * st] = (r[k * st] - ah * x0 - ch * xl) * frcp(bh);
     }
     r[0] = x0;
     r[(M - 1) * st] = xl;
 }
 
+// Wave 0 owns the 64 row segments of a tile (lane -> segment lane/16 of row
+// lane%16, conflict-free with the padded rows), wave 1 its 64 column segments.
 __global__ __launch_bounds__(NT) void k_reduce(SolveArgs A) {
     __shared__ SolveTile s;
     const Dom &d = A.d;
@@ -366,21 +390,26 @@ __global__ __launch_bounds__(NT) void k_reduce(SolveArgs A) {
         s.rx[cy][cx] = A.rx[o];
         s.ry[cy][cx] = A.ry[o];
     }
-    fill_coefs(A, s, i0, j0, true);
-    if (tid < TY) {
-        float4 first, last;
-        seg_eliminate<TX>(&s.rx[tid][0], &s.xa[tid][0], &s.xb[tid][0], &s.xc[tid][0], 1, first, last);
-        float4 *red = A.redx + (size_t)(j0 + tid) * d.nu + 2 * bx;
-        red[0] = first;
-        red[1] = last;
-    } else if (tid >= 64 && tid < 64 + TX) {
-        const int c = tid - 64;
-        float4 first, last;
-        seg_eliminate<TY>(&s.ry[0][c], &s.ya[0][c], &s.yb[0][c], &s.yc[0][c], TX, first, last);
-        float4 *red = A.redy + (size_t)(i0 + c) * d.nv + 2 * by;
-        red[0] = first;
-        red[1] = last;
+    load_depths(d, s, i0, j0);
+    float4 first, last;
+    float4 *red;
+    if (tid < 64) {
+        const int row = tid % 16, seg = tid / 16, k0 = seg * MX;
+        float a[MX], b[MX], c[MX];
+        float *r = &s.rx[row][k0];
+        seg_coefs<MX>(A, s, i0, j0, 0, k0, row, a, b, c, r, 1);
+        seg_eliminate<MX>(r, 1, a, b, c, first, last);
+        red = A.redx + (size_t)(j0 + row) * d.nu + 2 * (bx * (TX / MX) + seg);
+    } else {
+        const int col = tid - 64;
+        float a[TY], b[TY], c[TY];
+        float *r = &s.ry[0][col];
+        seg_coefs<TY>(A, s, i0, j0, 1, col, 0, a, b, c, r, TXP);
+        seg_eliminate<TY>(r, TXP, a, b, c, first, last);
+        red = A.redy + (size_t)(i0 + col) * d.nv + 2 * by;
     }
+    red[0] = first;
+    red[1] = last;
     __syncthreads();
     for (int k = tid; k < TX * TY; k += NT) {
         const int cx = k % TX, cy = k / TX;
@@ -390,9 +419,14 @@ __global__ __launch_bounds__(NT) void k_reduce(SolveArgs A) {
     }
 }
 
-// Parallel cyclic reduction of one reduced system (rows first, then columns).
-__global__ __launch_bounds__(NT) void k_pcr(SolveArgs A) {
-    __shared__ float4 buf[2][NRED_MAX];
+// Parallel cyclic reduction of one reduced system (rows first, then
+// columns): each thread keeps its equations (k = tid + j * PCR_NT) in
+// registers; one LDS copy of the system (dynamic size N) is read, then
+// overwritten, per reduction level.
+constexpr int PCR_NT = 128;
+constexpr int PCR_EPL = NRED_MAX / PCR_NT;  // equations per thread at most
+__global__ __launch_bounds__(PCR_NT) void k_pcr(SolveArgs A) {
+    extern __shared__ float4 buf[];
     const Dom &d = A.d;
     int sys = blockIdx.x, N;
     const float4 *src;
@@ -408,23 +442,36 @@ __global__ __launch_bounds__(NT) void k_pcr(SolveArgs A) {
         dst = A.soly + (size_t)sys * N;
     }
     const int tid = threadIdx.x;
-    for (int k = tid; k < N; k += NT) buf[0][k] = src[k];
+    const int nmine = (N - tid + PCR_NT - 1) / PCR_NT;
+    float4 eq[PCR_EPL];
+#pragma unroll
+    for (int j = 0; j < PCR_EPL; ++j)
+        if (j < nmine) {
+            eq[j] = src[tid + j * PCR_NT];
+            buf[tid + j * PCR_NT] = eq[j];
+        }
     __syncthreads();
-    int cur = 0;
     const float4 id = make_float4(0.f, 1.f, 0.f, 0.f);
     for (int st = 1; st < N; st <<= 1) {
-        for (int k = tid; k < N; k += NT) {
-            const float4 e = buf[cur][k];
-            const float4 m = k - st >= 0 ? buf[cur][k - st] : id;
-            const float4 p = k + st < N ? buf[cur][k + st] : id;
-            const float al = -e.x / m.y, ga = -e.z / p.y;
-            buf[cur ^ 1][k] = make_float4(al * m.x, e.y + al * m.z + ga * p.x, ga * p.z,
-                                          e.w + al * m.w + ga * p.w);
-        }
-        cur ^= 1;
+#pragma unroll
+        for (int j = 0; j < PCR_EPL; ++j)
+            if (j < nmine) {
+                const int k = tid + j * PCR_NT;
+                const float4 e = eq[j];
+                const float4 m = k - st >= 0 ? buf[k - st] : id;
+                const float4 p = k + st < N ? buf[k + st] : id;
+                const float al = -e.x * frcp(m.y), ga = -e.z * frcp(p.y);
+                eq[j] = make_float4(al * m.x, e.y + al * m.z + ga * p.x, ga * p.z, e.w + al * m.w + ga * p.w);
+            }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < PCR_EPL; ++j)
+            if (j < nmine) buf[tid + j * PCR_NT] = eq[j];
         __syncthreads();
     }
-    for (int k = tid; k < N; k += NT) dst[k] = buf[cur][k].w / buf[cur][k].y;
+#pragma unroll
+    for (int j = 0; j < PCR_EPL; ++j)
+        if (j < nmine) dst[tid + j * PCR_NT] = eq[j].w / eq[j].y;
 }
 
 __global__ __launch_bounds__(NT) void k_expand(SolveArgs A) {
@@ -438,14 +485,19 @@ __global__ __launch_bounds__(NT) void k_expand(SolveArgs A) {
         s.rx[cy][cx] = A.rx[o];
         s.ry[cy][cx] = A.ry[o];
     }
-    fill_coefs(A, s, i0, j0, false);
-    if (tid < TY) {
-        const float *sol = A.solx + (size_t)(j0 + tid) * d.nu + 2 * bx;
-        seg_expand<TX>(&s.rx[tid][0], &s.xa[tid][0], &s.xb[tid][0], &s.xc[tid][0], 1, sol[0], sol[1]);
-    } else if (tid >= 64 && tid < 64 + TX) {
-        const int c = tid - 64;
-        const float *sol = A.soly + (size_t)(i0 + c) * d.nv + 2 * by;
-        seg_expand<TY>(&s.ry[0][c], &s.ya[0][c], &s.yb[0][c], &s.yc[0][c], TX, sol[0], sol[1]);
+    load_depths(d, s, i0, j0);
+    if (tid < 64) {
+        const int row = tid % 16, seg = tid / 16, k0 = seg * MX;
+        const float *sol = A.solx + (size_t)(j0 + row) * d.nu + 2 * (bx * (TX / MX) + seg);
+        float a[MX], b[MX], c[MX];
+        seg_coefs<MX>(A, s, i0, j0, 0, k0, row, a, b, c, nullptr, 1);
+        seg_expand<MX>(&s.rx[row][k0], 1, a, b, c, sol[0], sol[1]);
+    } else {
+        const int col = tid - 64;
+        const float *sol = A.soly + (size_t)(i0 + col) * d.nv + 2 * by;
+        float a[TY], b[TY], c[TY];
+        seg_coefs<TY>(A, s, i0, j0, 1, col, 0, a, b, c, nullptr, TXP);
+        seg_expand<TY>(&s.ry[0][col], TXP, a, b, c, sol[0], sol[1]);
     }
     __syncthreads();
     int bad = 0;
@@ -454,11 +506,10 @@ __global__ __launch_bounds__(NT) void k_expand(SolveArgs A) {
         if (i >= d.nx || j >= d.ny) continue;
         const size_t o = (size_t)j * d.pitch + i;
         float P = A.pbase[o] + s.rx[cy][cx], Q = A.qbase[o] + s.ry[cy][cx], e = A.eta[o];
-        const float Dc = 0.25f * ((s.D[cy + 1][cx + 1] + s.D[cy + 1][cx + 2]) +
-                                  (s.D[cy + 2][cx + 1] + s.D[cy + 2][cx + 2]));
+        const float Dc = s.dc[cy + 1][cx + 1];
         const float h = e + Dc, h2 = h * h, h4 = h2 * h2;
         if (h4 < d.eps) {  // shoreline: discharge = h * desingularized velocity
-            const float f = 1.41421356237f * h2 * rsqrtf(h4 + d.eps);
+            const float f = 1.41421356237f * h2 * frsq(h4 + d.eps);
             P *= f;
             Q *= f;
         }
