@@ -26,16 +26,19 @@ HBM_PEAK_GBS = 8000.0
 # the default configuration (linear F* extrapolation, two correctors):
 #   predictor: reads eta, P, Q, corner depth, history n-1 (E, F, G, F*, G*),
 #              history n-2 (E, F, G); writes history n (5), corrector bases (3),
-#              eta, U*, V*                                   -> 12 + 11 = 23
-#   corrector: reads eta, P, Q, depth, bases (3); writes eta, U*, V* -> 7 + 3 = 10
-#   reduce:    reads U*, V*, depth; writes eliminated U*, V*, reduced equations
-#              (4 words per 2 ends of a 64-cell row / 16-cell column segment)
-#                                                            -> 3 + 2 + 0.625
-#   pcr:       reads the reduced equations, writes their solutions -> 0.78
-#   expand:    reads eliminated U*, V*, depth, eta, end values; writes P, Q
-#                                                            -> 4.16 + 2
+#              eta, dU*, dV*                                 -> 12 + 11 = 23
+#   corrector: reads eta, P, Q, depth, bases (3); writes eta, dU*, dV* -> 7 + 3 = 10
+#   reduce:    reads dU*, dV*, depth; writes the eliminated values and the
+#              reduced equations (two 4-word equations per 16-cell row segment
+#              and per 16-cell column segment)             -> 3 + 2 + 1 = 6
+#   pcr:       reads the reduced equations, writes their solutions -> 1 + 0.25
+#   expand:    reads eliminated values (2), P^n, Q^n, eta, depth, end values;
+#              writes P, Q                                  -> 6.25 + 2
 ALG_WORDS = {"k_stencil[predictor]": 23.0, "k_stencil[corrector]": 10.0,
-             "k_reduce": 5.625, "k_pcr": 0.78125, "k_expand": 6.15625}
+             "k_reduce": 6.0, "k_pcr": 1.25, "k_expand": 8.25}
+# kernel function -> its launch classes
+FUNCS = {"k_stencil": ("k_stencil[predictor]", "k_stencil[corrector]"), "k_reduce": ("k_reduce",),
+         "k_pcr": ("k_pcr",), "k_expand": ("k_expand",)}
 
 
 def parse():
@@ -84,12 +87,20 @@ def main():
     from paper_1611_05984_amd import workloads as wl
 
     torch.cuda.set_device(0)
+    copy_gbs = None
     if args.copy_calib:
+        # 256 MiB device-to-device copy: calibrates the HBM byte counters of a
+        # profiled run and gives the practical copy bandwidth of this GPU
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
-        for _ in range(3):
+        dst.copy_(src)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(5):
             dst.copy_(src)
+        ev1.record()
         torch.cuda.synchronize()
+        copy_gbs = 5 * 2 * src.numel() * 4 / (ev0.elapsed_time(ev1) / 1e3) / 1e9
         del src, dst
     w = wl.config3(n=args.n)
     D = ws.Domain(w.nx, w.ny, w.dx, w.dy, w.dt, w.z, device="cuda:0")
@@ -119,10 +130,12 @@ def main():
     prof = D.profile_collect()
     D.profile(False)
     tot = sum(ms for ms, n in prof.values())
-    dom_name = max(prof, key=lambda k: prof[k][0])
-    dom_ms, dom_n = prof[dom_name]
+    fsum = {f: (sum(prof[c][0] for c in cs), sum(prof[c][1] for c in cs),
+                sum(ALG_WORDS[c] * prof[c][1] for c in cs)) for f, cs in FUNCS.items()}
+    dom_name = max(fsum, key=lambda f: fsum[f][0])
+    dom_ms, dom_n, dom_words = fsum[dom_name]
     avg_s = dom_ms / dom_n / 1e3
-    alg_bytes = ALG_WORDS[dom_name] * 4.0 * cells
+    alg_bytes = dom_words / dom_n * 4.0 * cells
     achieved = alg_bytes / avg_s / 1e9
     step_words = (ALG_WORDS["k_stencil[predictor]"] + 2 * ALG_WORDS["k_stencil[corrector]"] +
                   3 * (ALG_WORDS["k_reduce"] + ALG_WORDS["k_pcr"] + ALG_WORDS["k_expand"]))
@@ -157,6 +170,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": dom_name, "kernel_ms_avg": dom_ms / dom_n,
                      "alg_bytes_per_launch": alg_bytes},
+        "copy_GBs": copy_gbs,
         "step_hbm": {"alg_bytes_per_cell_step": step_words * 4,
                      "alg_GBs": value * step_words * 4 / 1e9,
                      "frac_of_peak": value * step_words * 4 / 1e9 / HBM_PEAK_GBS},

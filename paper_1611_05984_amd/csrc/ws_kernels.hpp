@@ -77,6 +77,9 @@ __global__ __launch_bounds__(64 * SWG) void k_stencil(StencilArgs A) {
     const int j0 = blockIdx.y * SY;
     const float th = d.theta, g = d.g, eps = d.eps;
     const float rdx = d.rdx, rdy = d.rdy, Bd = d.Bd, B3 = d.Bd + 1.f / 3.f;
+    // strips whose cells and corners (with halo) all lie inside the domain
+    // load without boundary handling
+    const bool interior = c0 >= 1 && c0 + 64 <= d.nx - 1 && j0 >= 2 && j0 + SY + 1 <= d.ny - 1;
 
     // sliding windows (row index relative to the row r loaded this iteration)
     float e0 = 0.f, e1 = 0.f, e2 = 0.f, e3 = 0.f, e4 = 0.f;  // eta rows r-4 .. r
@@ -84,10 +87,11 @@ __global__ __launch_bounds__(64 * SWG) void k_stencil(StencilArgs A) {
     float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;            // Q rows r-3 .. r
     float he0 = 0.f, he1 = 0.f, he2 = 0.f, hp0 = 0.f, hp1 = 0.f, hp2 = 0.f;  // halo rows r-2 .. r
     float hq0 = 0.f, hq1 = 0.f, hq2 = 0.f;
-    float Dl0 = 0.f, Dl1 = 0.f, Dl2 = 0.f, Dl3 = 0.f;        // corner depth at col, rows r-3 .. r
-    float Dr0 = 0.f, Dr1 = 0.f, Dr2 = 0.f, Dr3 = 0.f;        // corner depth at col+1
+    float Dl1 = 0.f, Dl2 = 0.f, Dl3 = 0.f;                   // corner depth at col, rows r-2 .. r
+    float Dr1 = 0.f, Dr2 = 0.f, Dr3 = 0.f;                   // corner depth at col+1
     F3 hiy_prev = {0.f, 0.f, 0.f};                           // y-reconstruction, north side of row r-2
     float Hs0 = 0.f, Hs1 = 0.f, Hs2 = 0.f;                   // flux through the south face of row r-2
+    float Dcm = 0.f, Dc0 = 0.f;                              // cell depth D of rows r-3, r-2
 
     for (int it = 0; it < SY + 4; ++it) {
         const int r = j0 - 2 + it;
@@ -95,13 +99,33 @@ __global__ __launch_bounds__(64 * SWG) void k_stencil(StencilArgs A) {
         p0 = p1; p1 = p2; p2 = p3;
         q0 = q1; q1 = q2; q2 = q3;
         he0 = he1; he1 = he2; hp0 = hp1; hp1 = hp2; hq0 = hq1; hq1 = hq2;
-        Dl0 = Dl1; Dl1 = Dl2; Dl2 = Dl3;
-        Dr0 = Dr1; Dr1 = Dr2; Dr2 = Dr3;
-        load_cell(d, A.ein, A.pin, A.qin, col, r, e4, p3, q3);
-        if (halo_lane) load_cell(d, A.ein, A.pin, A.qin, hcol, r, he2, hp2, hq2);
-        Dl3 = corner_D(d, col, r);
-        Dr3 = corner_D(d, col + 1, r);
-        if (it < 2) continue;
+        Dl1 = Dl2; Dl2 = Dl3;
+        Dr1 = Dr2; Dr2 = Dr3;
+        if (interior) {
+            const int o = r * d.pitch + col, oh = r * d.pitch + hcol, oz = r * d.zpitch + col;
+            e4 = A.ein[o];
+            p3 = A.pin[o];
+            q3 = A.qin[o];
+            if (halo_lane) {
+                he2 = A.ein[oh];
+                hp2 = A.pin[oh];
+                hq2 = A.qin[oh];
+            }
+            Dl3 = d.D[oz];
+            Dr3 = d.D[oz + 1];
+        } else {
+            load_cell(d, A.ein, A.pin, A.qin, col, r, e4, p3, q3);
+            if (halo_lane) load_cell(d, A.ein, A.pin, A.qin, hcol, r, he2, hp2, hq2);
+            Dl3 = corner_D(d, col, r);
+            Dr3 = corner_D(d, col + 1, r);
+        }
+        // still-water depth D of the cell in row r-1
+        const float Dcp = 0.25f * ((Dl2 + Dr2) + (Dl3 + Dr3));
+        if (it < 2) {
+            Dcm = Dc0;
+            Dc0 = Dcp;
+            continue;
+        }
 
         // y-reconstruction of row r-1 (normal discharge Q) and the flux
         // through its south face (between rows r-2 and r-1)
@@ -114,7 +138,7 @@ __global__ __launch_bounds__(64 * SWG) void k_stencil(StencilArgs A) {
         if (it >= 4) {  // update row u = r - 2
             const int u = r - 2;
             const bool out = lane >= 1 && lane <= 62 && col < d.nx && u < d.ny;
-            const size_t o = (size_t)u * d.pitch + col;
+            const int o = u * d.pitch + col;
             float E1v = 0.f, F1v = 0.f, G1v = 0.f, Fs1v = 0.f, Gs1v = 0.f, E2v = 0.f, F2v = 0.f, G2v = 0.f;
             float Fs2v = 0.f, Gs2v = 0.f, Sev = 0.f, SUv = 0.f, SVv = 0.f;
             if (out) {
@@ -127,7 +151,7 @@ __global__ __launch_bounds__(64 * SWG) void k_stencil(StencilArgs A) {
                 }
             }
             // cell and face still-water depths
-            const float Dc = 0.25f * ((Dl1 + Dr1) + (Dl2 + Dr2));
+            const float Dc = Dc0;
             const float Dw = 0.5f * (Dl1 + Dl2), De = 0.5f * (Dr1 + Dr2);
             const float Ds = 0.5f * (Dl1 + Dr1), Dn = Dys;
             // x-reconstruction of row u (normal discharge P); lanes 0 and 63
@@ -149,7 +173,7 @@ __global__ __launch_bounds__(64 * SWG) void k_stencil(StencilArgs A) {
 
             const float dep = fmaxf(Dc, 0.f);
             const float dxm = shr1(dep, dep), dxp = shl1(dep, dep);
-            const float dym = dcell4(Dl0, Dr0, Dl1, Dr1), dyp = dcell4(Dl2, Dr2, Dl3, Dr3);
+            const float dym = fmaxf(Dcm, 0.f), dyp = fmaxf(Dcp, 0.f);
             const float ddx = (dxp - dxm) * 0.5f * rdx, ddy = (dyp - dym) * 0.5f * rdy;
 
             if (d.model == BSNQ) {
@@ -221,6 +245,8 @@ __global__ __launch_bounds__(64 * SWG) void k_stencil(StencilArgs A) {
         Hs0 = Hn0;
         Hs1 = Hn1;
         Hs2 = Hn2;
+        Dcm = Dc0;
+        Dc0 = Dcp;
     }
 }
 
@@ -391,25 +417,27 @@ __global__ __launch_bounds__(NT) void k_reduce(SolveArgs A) {
         s.ry[cy][cx] = A.ry[o];
     }
     load_depths(d, s, i0, j0);
-    float4 first, last;
-    float4 *red;
     if (tid < 64) {
         const int row = tid % 16, seg = tid / 16, k0 = seg * MX;
         float a[MX], b[MX], c[MX];
+        float4 first, last;
         float *r = &s.rx[row][k0];
         seg_coefs<MX>(A, s, i0, j0, 0, k0, row, a, b, c, r, 1);
         seg_eliminate<MX>(r, 1, a, b, c, first, last);
-        red = A.redx + (size_t)(j0 + row) * d.nu + 2 * (bx * (TX / MX) + seg);
-    } else {
+        float4 *red = A.redx + (size_t)(j0 + row) * d.nu + 2 * (bx * (TX / MX) + seg);
+        red[0] = first;
+        red[1] = last;
+    } else if (tid < 128) {
         const int col = tid - 64;
         float a[TY], b[TY], c[TY];
+        float4 first, last;
         float *r = &s.ry[0][col];
         seg_coefs<TY>(A, s, i0, j0, 1, col, 0, a, b, c, r, TXP);
         seg_eliminate<TY>(r, TXP, a, b, c, first, last);
-        red = A.redy + (size_t)(i0 + col) * d.nv + 2 * by;
+        float4 *red = A.redy + (size_t)(i0 + col) * d.nv + 2 * by;
+        red[0] = first;
+        red[1] = last;
     }
-    red[0] = first;
-    red[1] = last;
     __syncthreads();
     for (int k = tid; k < TX * TY; k += NT) {
         const int cx = k % TX, cy = k / TX;
@@ -486,13 +514,24 @@ __global__ __launch_bounds__(NT) void k_expand(SolveArgs A) {
         s.ry[cy][cx] = A.ry[o];
     }
     load_depths(d, s, i0, j0);
+    constexpr int CPT = TX * TY / NT;  // epilogue cells per thread
+    float pre_e[CPT], pre_p[CPT], pre_q[CPT];
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+        const int k = tid + m * NT, cx = k % TX, cy = k / TX, i = i0 + cx, j = j0 + cy;
+        const int o = j * d.pitch + i;
+        const bool in = i < d.nx && j < d.ny;
+        pre_e[m] = in ? A.eta[o] : 0.f;
+        pre_p[m] = in ? A.pbase[o] : 0.f;
+        pre_q[m] = in ? A.qbase[o] : 0.f;
+    }
     if (tid < 64) {
         const int row = tid % 16, seg = tid / 16, k0 = seg * MX;
         const float *sol = A.solx + (size_t)(j0 + row) * d.nu + 2 * (bx * (TX / MX) + seg);
         float a[MX], b[MX], c[MX];
         seg_coefs<MX>(A, s, i0, j0, 0, k0, row, a, b, c, nullptr, 1);
         seg_expand<MX>(&s.rx[row][k0], 1, a, b, c, sol[0], sol[1]);
-    } else {
+    } else if (tid < 128) {
         const int col = tid - 64;
         const float *sol = A.soly + (size_t)(i0 + col) * d.nv + 2 * by;
         float a[TY], b[TY], c[TY];
@@ -501,11 +540,12 @@ __global__ __launch_bounds__(NT) void k_expand(SolveArgs A) {
     }
     __syncthreads();
     int bad = 0;
-    for (int k = tid; k < TX * TY; k += NT) {
-        const int cx = k % TX, cy = k / TX, i = i0 + cx, j = j0 + cy;
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+        const int k = tid + m * NT, cx = k % TX, cy = k / TX, i = i0 + cx, j = j0 + cy;
         if (i >= d.nx || j >= d.ny) continue;
-        const size_t o = (size_t)j * d.pitch + i;
-        float P = A.pbase[o] + s.rx[cy][cx], Q = A.qbase[o] + s.ry[cy][cx], e = A.eta[o];
+        const int o = j * d.pitch + i;
+        float P = pre_p[m] + s.rx[cy][cx], Q = pre_q[m] + s.ry[cy][cx], e = pre_e[m];
         const float Dc = s.dc[cy + 1][cx + 1];
         const float h = e + Dc, h2 = h * h, h4 = h2 * h2;
         if (h4 < d.eps) {  // shoreline: discharge = h * desingularized velocity

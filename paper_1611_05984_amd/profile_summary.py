@@ -1,0 +1,121 @@
+"""Summarize rocprofv3 result databases of a wavestep run.
+
+Usage:
+  python -m paper_1611_05984_amd.profile_summary --trace KT.db [--fetch F.db --write W.db]
+         [--cells N] [--out summary.txt] [--traffic-json traffic.json --command "..."]
+
+--trace: database of `rocprofv3 --kernel-trace --stats`; prints per-kernel calls,
+average and total duration.
+--fetch/--write: databases of `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE`
+runs of the same command.  The byte counters are calibrated against the device
+copy in the same run (bench.py --copy-calib copies 256 MiB with hipMemcpy,
+i.e. the runtime's copyBuffer kernel): scale = known bytes / counter bytes of
+that dispatch, per counter.  Per kernel class the calibrated bytes per dispatch
+are reported (words per cell when --cells is given).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sqlite3
+from collections import defaultdict
+
+COPY_BYTES = 64 * 1024 * 1024 * 4  # bench.py --copy-calib: 64 Mi floats
+
+
+def _q(db, sql, args=()):
+    con = sqlite3.connect(db)
+    try:
+        return con.execute(sql, args).fetchall()
+    finally:
+        con.close()
+
+
+def trace_table(db):
+    """(name, calls, total us, average us, percent) per kernel; the database's
+    top_kernels view reports durations in microseconds."""
+    rows = _q(db, "select name, total_calls, total_duration, average, percentage from top_kernels")
+    return [(n, int(c), float(t), float(a), float(p)) for n, c, t, a, p in rows]
+
+
+def counter_values(db, counter):
+    rows = _q(db, "select kernel_name, value from counters_collection where counter_name=? "
+                  "order by dispatch_id", (counter,))
+    out = defaultdict(list)
+    for name, v in rows:
+        out[name].append(float(v) * 1024.0)  # KiB -> bytes
+    return out
+
+
+def calib(values):
+    copies = [v for k, vs in values.items() if "copyBuffer" in k for v in vs]
+    big = max(copies) if copies else 0.0
+    return COPY_BYTES / big if big > 0 else None
+
+
+def short(name):
+    return name.split("(")[0].replace("ws::", "")
+
+
+def source_hash(root):
+    h = hashlib.sha256()
+    for f in ("ws_device.hpp", "ws_kernels.hpp", "wavestep.hip"):
+        h.update(open(os.path.join(root, "paper_1611_05984_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--cells", type=int, default=0)
+    ap.add_argument("--out")
+    ap.add_argument("--traffic-json")
+    ap.add_argument("--command", default="")
+    ap.add_argument("--kernel", default="k_stencil")
+    ap.add_argument("--skip", type=int, default=2,
+                    help="leading dispatches per kernel left out of the averages (Euler start-up)")
+    a = ap.parse_args()
+    lines = []
+    if a.command:
+        lines.append("command: " + a.command)
+    lines.append("%-32s %7s %12s %12s %7s" % ("kernel", "calls", "avg_us", "total_us", "pct"))
+    for n, c, t, avg, p in trace_table(a.trace):
+        lines.append("%-32s %7d %12.1f %12.1f %6.1f%%" % (short(n)[:32], c, avg, t, p))
+    traffic = {}
+    if a.fetch and a.write:
+        fv, wv = counter_values(a.fetch, "FETCH_SIZE"), counter_values(a.write, "WRITE_SIZE")
+        fs, wsc = calib(fv), calib(wv)
+        lines.append("")
+        lines.append("HBM bytes per dispatch (FETCH_SIZE x %.3f, WRITE_SIZE x %.3f; factors from the "
+                     "%d-byte device copy)" % (fs or 0, wsc or 0, COPY_BYTES))
+        for name in sorted(fv):
+            if not name.startswith("ws::"):
+                continue
+            rd = [v * fs for v in fv[name]][a.skip:]
+            wr = [v * wsc for v in wv.get(name, [])][a.skip:]
+            n = min(len(rd), len(wr))
+            per = [(rd[i], wr[i]) for i in range(n)]
+            avg_r, avg_w = sum(x for x, _ in per) / n, sum(y for _, y in per) / n
+            txt = "%-24s dispatches %3d  read %9.3e B  write %9.3e B" % (short(name), n, avg_r, avg_w)
+            if a.cells:
+                txt += "  (%.2f + %.2f words/cell)" % (avg_r / a.cells / 4, avg_w / a.cells / 4)
+            lines.append(txt)
+            traffic[short(name)] = {"read": avg_r, "write": avg_w, "dispatches": n,
+                                    "per_dispatch": per}
+    text = "\n".join(lines)
+    print(text)
+    if a.out:
+        open(a.out, "w").write(text + "\n")
+    if a.traffic_json and a.kernel in traffic:
+        root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+        t = traffic[a.kernel]
+        json.dump({"kernel": a.kernel, "bytes_per_launch": t["read"] + t["write"],
+                   "read": t["read"], "write": t["write"], "dispatches": t["dispatches"],
+                   "source_hash": source_hash(root), "command": a.command},
+                  open(a.traffic_json, "w"), indent=1)
+
+
+if __name__ == "__main__":
+    main()
