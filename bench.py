@@ -51,6 +51,11 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a 256 MiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-vs-plain ensemble measurement")
+    ap.add_argument("--ens-steps", type=int, default=30, help="timed steps of the ensemble runs")
+    ap.add_argument("--no-k-variants", action="store_true",
+                    help="skip the K = 0 and K = 1 corrector-count rates")
     return ap.parse_args()
 
 
@@ -72,6 +77,81 @@ def cpu_baseline(w, steps):
             "kind": "oracle",
             "sample": "%s, %d full steps (predictor + 2 correctors) after the 2 Euler "
                       "start-up steps, FP64, %.1f s" % (w.name, steps, dt)}
+
+
+def _make(ws, w, **params):
+    d = ws.Domain(w.nx, w.ny, w.dx, w.dy, w.dt, w.z, device="cuda:0", **params)
+    for s, side in enumerate(w.sides):
+        if side.kind != 0:
+            d.set_boundary(s, side.kind, side.width, side.amp, side.period, side.theta,
+                           side.phase or None)
+    for (H, th, x0, y0) in w.solitary:
+        d.add_solitary(H, th, x0, y0)
+    return d
+
+
+def _timed(torch, fn, steps):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fn(steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def batched_vs_plain(args, torch, ws, wl):
+    """Ensemble of 256 uneven domains: batched stepping (one launch per phase
+    for all domains, one graph replay per step) against per-domain stepping
+    with the single-domain kernels on one stream, eager and graph-captured."""
+    ens = wl.config4()
+    cells = sum(w.cells for w in ens)
+    doms = [_make(ws, w) for w in ens]
+    B = ws.Batch(len(doms))
+    for d in doms:
+        B.attach(d)
+    B.advance(4)                       # Euler start-up + graph capture, untimed
+    B.sync()
+    n = args.ens_steps
+    t_b = _timed(torch, lambda k: (B.advance(k), B.sync()), n)
+    B.close()                          # domains usable alone again
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        for d in doms:
+            d.advance(1, stream=st)
+    t_p = _timed(torch, lambda k: [d.advance(k_, stream=st) for k_ in [1] * k for d in doms], n)
+    # per-domain launches captured as a graph: three steps (the period of the
+    # history ring and buffer rotation for two correctors), replayed
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=st):
+        for _ in range(3):
+            for d in doms:
+                d.advance(1, stream=st)
+    reps = max(1, n // 3)
+    t_g = _timed(torch, lambda k: [g.replay() for _ in range(k)], reps)
+    health = [d.query()[2] for d in doms]
+    del g
+    return {"workload": "ensemble256_U256-1024_flat-or-beach_solitary", "domains": len(doms),
+            "cells": cells, "steps": n,
+            "batched": cells * n / t_b, "plain_eager": cells * n / t_p,
+            "plain_graph": cells * 3 * reps / t_g,
+            "batched_over_plain_graph": (cells * n / t_b) / (cells * 3 * reps / t_g),
+            "batched_over_plain_eager": (cells * n / t_b) / (cells * n / t_p),
+            "unit": "cell-updates/s", "healthy": all(h == 0 for h in health)}
+
+
+def k_variants(args, torch, ws, wl):
+    """Rates of the big-domain workload with K = 0 and K = 1 correctors."""
+    w = wl.config3(n=args.n)
+    out = {}
+    for K in (0, 1):
+        d = _make(ws, w, n_corr=K)
+        d.advance(5)
+        n = max(10, args.steps // 4)
+        t = _timed(torch, lambda k: d.advance(k), n)
+        out["K%d" % K] = w.nx * w.ny * n / t
+        d.close()
+        del d
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -177,6 +257,15 @@ def main():
         "kernels": kernels,
         "sim": {"step": step, "t_s": tsim},
     }
+    D.close()
+    del D
+    torch.cuda.empty_cache()
+    if not args.no_k_variants:
+        print("bench: K = 0, 1 rates", file=sys.stderr, flush=True)
+        out["k_variants"] = k_variants(args, torch, ws, wl)
+    if not args.no_batched:
+        print("bench: ensemble batched vs plain", file=sys.stderr, flush=True)
+        out["ensemble"] = batched_vs_plain(args, torch, ws, wl)
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)

@@ -176,6 +176,31 @@ ws_status ws_profile_enable(ws_domain *d, int32_t on);
 ws_status ws_profile_collect(ws_domain *d, void *stream, double *total_ms, int64_t *launches,
                              int32_t n);
 
+/* ---- Batches: many independent domains advanced together (the ensemble
+ * and serving forms).  Each phase of a pass is one launch for all attached
+ * domains; the per-domain step bookkeeping (Euler start-up, history slots,
+ * buffer rotation) lives on the device, so a step is captured once as a HIP
+ * graph on a non-null stream and replayed.  Domains of any size and at any
+ * step index mix in one batch.  The caller allocates the batch workspace
+ * (ws_batch_workspace_bytes) and keeps every attached domain alive.
+ * While attached, a domain is advanced only by ws_batch_advance; after it,
+ * ws_batch_sync must run before any per-domain call on an attached domain
+ * (they return WS_EBUSY until then).  Edits, hot starts and boundary changes
+ * on an attached, synced domain are allowed and picked up by the next
+ * ws_batch_advance. */
+size_t ws_batch_workspace_bytes(int32_t max_domains);
+ws_status ws_batch_create(int32_t max_domains, void *workspace_dev, size_t workspace_bytes,
+                          ws_batch **out);
+ws_status ws_batch_destroy(ws_batch *b);
+/* Attach a domain (WS_EBUSY if the batch is full or the domain attached elsewhere). */
+ws_status ws_batch_attach(ws_batch *b, ws_domain *d, int32_t *slot);
+ws_status ws_batch_detach(ws_batch *b, int32_t slot);
+/* Advance every attached domain by nsteps full steps.  Asynchronous. */
+ws_status ws_batch_advance(ws_batch *b, int64_t nsteps, void *stream);
+/* Synchronize `stream` and bring the attached domains' step, time and state
+ * buffer index up to date on the host. */
+ws_status ws_batch_sync(ws_batch *b, void *stream);
+
 /* Thread-local description of the last error. */
 const char *ws_last_error(void);
 

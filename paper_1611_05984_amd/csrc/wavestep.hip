@@ -11,7 +11,7 @@
 #include <vector>
 
 #include "../../include/wavestep.h"
-#include "ws_kernels.hpp"
+#include "ws_batch.hpp"
 
 using namespace ws;
 
@@ -61,14 +61,28 @@ struct ws_domain {
     double t;
     bool prof_on;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof;  // (class, start, stop)
+    ws_batch *batch;               // batch this domain is attached to, if any
+    int bidx;                      // its index in the batch's device tables
+    bool stale;                    // the batch has advanced it since the last ws_batch_sync
+    bool vdirty;                   // pass argument tables must be rewritten
+    StencilArgs *vsa;              // pass argument tables (device), batch use only
+    SolveArgs *vso;
+    int nvar;
 };
+
+static ws_status busy_check(const ws_domain *d, const char *who) {
+    if (d->batch && d->stale) return fail(WS_EBUSY, "%s: domain advanced by its batch; call ws_batch_sync first", who);
+    return WS_OK;
+}
+static void batch_touch(ws_domain *d);
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 static int roundup(int x, int m) { return (x + m - 1) / m * m; }
 
 struct Layout {
     int nxp, nyp, pitch, zpitch, nu, nv, gl;
-    size_t field, corners, redx, redy, solx, soly, ghost, tabs, misc, total;
+    size_t field, corners, redx, redy, solx, soly, ghost, tabs, misc, vtab, total;
+    int nvar;
 };
 
 static bool grid_ok(const ws_grid *g) {
@@ -96,8 +110,12 @@ static Layout layout(const ws_grid *g) {
     L.ghost = align256(sizeof(float) * 4 * 2 * 3 * (size_t)L.gl);
     L.tabs = align256(sizeof(double) * MAXC * TABW);
     L.misc = 256;
+    // pass argument tables for batched stepping: 9 Euler start-up variants
+    // (state buffer x step mod 3) and 9 x (n_corr + 1) passes of full steps
+    L.nvar = 9 * (g->n_corr + 2);
+    L.vtab = align256(L.nvar * (sizeof(StencilArgs) + sizeof(SolveArgs)));
     L.total = 29 * L.field + 2 * L.corners + L.redx + L.redy + L.solx + L.soly + 2 * L.ghost +
-              4 * L.tabs + L.misc;
+              4 * L.tabs + L.misc + L.vtab;
     return L;
 }
 
@@ -328,6 +346,10 @@ extern "C" ws_status ws_domain_init(const ws_grid *g, const float *z_corners_dev
     char *misc = take(L.misc);
     d->health = (int *)misc;
     d->scal = (double *)(misc + 64);
+    d->nvar = L.nvar;
+    d->vsa = (StencilArgs *)take(L.vtab);
+    d->vso = (SolveArgs *)(d->vsa + L.nvar);
+    d->vdirty = true;
     for (int s = 0; s < 4; ++s) { d->side_type[s] = WS_BC_SOLID; d->side_width[s] = 2; }
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipMemsetAsync(d->base, 0, L.total, st);
@@ -369,6 +391,7 @@ static void prof_clear(ws_domain *d) {
 }
 
 extern "C" ws_status ws_domain_destroy(ws_domain *d) {
+    if (d && d->batch) return fail(WS_EBUSY, "ws_domain_destroy: detach the domain from its batch first");
     if (d) prof_clear(d);
     delete d;
     return WS_OK;
@@ -416,6 +439,7 @@ struct ProfScope {
 
 extern "C" ws_status ws_set_boundary(ws_domain *d, int32_t side, const ws_boundary *b) {
     if (!d || !b || side < 0 || side > 3) return fail(WS_EINVAL, "ws_set_boundary: bad argument");
+    if (busy_check(d, "ws_set_boundary") != WS_OK) return WS_EBUSY;
     if (b->type < 0 || b->type > 2) return fail(WS_EINVAL, "ws_set_boundary: bad type %d", b->type);
     const int nc = b->type == WS_BC_WAVES ? b->n_comp : 0;
     if (nc < 0 || nc > MAXC) return fail(WS_EINVAL, "ws_set_boundary: n_comp %d out of range", b->n_comp);
@@ -451,24 +475,28 @@ extern "C" ws_status ws_set_boundary(ws_domain *d, int32_t side, const ws_bounda
     }
     HIPCHK(hipMemcpy(d->tab[side], tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
     d->side_ncomp[side] = nc;
+    batch_touch(d);
     return WS_OK;
 }
 
 extern "C" ws_status ws_set_state(ws_domain *d, const float *w, const float *P, const float *Q,
                                   int32_t pitch, double t, void *stream) {
     if (!d || !w || !P || !Q || pitch < d->g.nx) return fail(WS_EINVAL, "ws_set_state: bad argument");
+    if (busy_check(d, "ws_set_state") != WS_OK) return WS_EBUSY;
     Dom m = make_dom(d);
     hipLaunchKernelGGL(k_set_state, cells_grid(d->g.nx, d->g.ny), dim3(256), 0, (hipStream_t)stream, m, w, P,
                        Q, pitch, (float)d->g.still_water, d->st[d->cur][0], d->st[d->cur][1], d->st[d->cur][2]);
     HIPCHK(hipGetLastError());
     d->t = t;
     d->step = 0;
+    batch_touch(d);
     return WS_OK;
 }
 
 extern "C" ws_status ws_read(ws_domain *d, int32_t what, float *first, float *P, float *Q,
                              int32_t pitch, void *stream) {
     if (!d || pitch < d->g.nx || (what != WS_READ_W && what != WS_READ_H)) return fail(WS_EINVAL, "ws_read: bad argument");
+    if (busy_check(d, "ws_read") != WS_OK) return WS_EBUSY;
     Dom m = make_dom(d);
     hipLaunchKernelGGL(k_read, cells_grid(d->g.nx, d->g.ny), dim3(256), 0, (hipStream_t)stream, m,
                        d->st[d->cur][0], d->st[d->cur][1], d->st[d->cur][2], what, (float)d->g.still_water,
@@ -480,6 +508,7 @@ extern "C" ws_status ws_read(ws_domain *d, int32_t what, float *first, float *P,
 extern "C" ws_status ws_add_solitary(ws_domain *d, double H, double theta, double x0, double y0,
                                      void *stream) {
     if (!d) return fail(WS_EINVAL, "ws_add_solitary: NULL domain");
+    if (busy_check(d, "ws_add_solitary") != WS_OK) return WS_EBUSY;
     hipStream_t st = (hipStream_t)stream;
     // still water depth of the bilinear bottom at (x0, y0)
     double fx = x0 / d->g.dx, fy = y0 / d->g.dy;
@@ -506,6 +535,7 @@ extern "C" ws_status ws_add_solitary(ws_domain *d, double H, double theta, doubl
 extern "C" ws_status ws_apply_edit(ws_domain *d, int32_t kind, double x0, double y0, double amp,
                                    double sigma, void *stream) {
     if (!d || !(sigma > 0.0)) return fail(WS_EINVAL, "ws_apply_edit: bad argument");
+    if (busy_check(d, "ws_apply_edit") != WS_OK) return WS_EBUSY;
     hipStream_t st = (hipStream_t)stream;
     Dom m = make_dom(d);
     float *e = d->st[d->cur][0], *p = d->st[d->cur][1], *q = d->st[d->cur][2];
@@ -528,6 +558,7 @@ extern "C" ws_status ws_apply_edit(ws_domain *d, int32_t kind, double x0, double
     HIPCHK(hipStreamSynchronize(st));
     if (flag) return fail(WS_ENOTDD, "ws_apply_edit: terrain edit rejected (eq. 23 would lose diagonal dominance)");
     std::swap(d->D, d->Dnew);
+    batch_touch(d);
     m = make_dom(d);
     hipLaunchKernelGGL(k_shore_fix, cells_grid(d->g.nx, d->g.ny), dim3(256), 0, st, m, e, p, q);
     HIPCHK(hipGetLastError());
@@ -540,13 +571,36 @@ static dim3 strips(const ws_domain *d) {
 }
 
 // One predictor or corrector pass: stencil, then the partitioned solves.
-static ws_status run_pass(ws_domain *d, StencilArgs &sa, int base, int out, bool sponge,
-                          hipStream_t st) {
-    {
-        ProfScope p(d, st, sa.kind == 2 ? WS_K_CORRECTOR : WS_K_PREDICTOR);
-        hipLaunchKernelGGL(k_stencil, strips(d), dim3(64 * SWG), 0, st, sa);
-    }
-    SolveArgs so;
+// Arguments of pass p of a step.  cur: state buffer of the step's state;
+// sm: step index mod 3 (history slots); euler: one of the two start-up steps.
+static void pass_args(const ws_domain *d, const Dom &m, bool euler, int cur, int sm, int p, StencilArgs &sa,
+                      SolveArgs &so) {
+    const ws_grid &g = d->g;
+    const int K = euler ? 0 : g.n_corr;
+    const int n0 = (sm + 2) % 3, n1 = (sm + 1) % 3, n2 = sm;
+    const int a = cur, b = (a + 1) % 3, c = (a + 2) % 3;
+    const int in = p == 0 ? a : ((p & 1) ? b : c);
+    const int out = p == 0 ? b : ((p & 1) ? c : b);
+    std::memset(&sa, 0, sizeof sa);
+    sa.d = m;
+    sa.d.gh = d->ghost[p == 0 ? 0 : 1];
+    sa.ein = d->st[in][0]; sa.pin = d->st[in][1]; sa.qin = d->st[in][2];
+    sa.eout = d->st[out][0];
+    sa.rx = d->rx; sa.ry = d->ry;
+    sa.hE = d->hist[n0][0]; sa.hF = d->hist[n0][1]; sa.hG = d->hist[n0][2];
+    sa.hFs = d->hist[n0][3]; sa.hGs = d->hist[n0][4];
+    sa.E1 = d->hist[n1][0]; sa.F1 = d->hist[n1][1]; sa.G1 = d->hist[n1][2];
+    sa.Fs1 = d->hist[n1][3]; sa.Gs1 = d->hist[n1][4];
+    sa.E2 = d->hist[n2][0]; sa.F2 = d->hist[n2][1]; sa.G2 = d->hist[n2][2];
+    sa.Fs2 = d->hist[n2][3]; sa.Gs2 = d->hist[n2][4];
+    sa.Se = d->S[0]; sa.SU = d->S[1]; sa.SV = d->S[2];
+    sa.dt = (float)g.dt;
+    sa.x0 = sa.x1 = sa.x2 = 0.f;
+    if (g.fstar_extrap == 2) { sa.x0 = 2.f; sa.x1 = -3.f; sa.x2 = 1.f; }
+    else if (g.fstar_extrap == 1) { sa.x0 = 1.f; sa.x1 = -1.f; }
+    sa.kind = p == 0 ? (euler ? 0 : 1) : 2;
+    sa.write_S = (p == 0 && !euler && K > 0) ? 1 : 0;
+    std::memset(&so, 0, sizeof so);
     so.d = sa.d;
     so.rx = d->rx;
     so.ry = d->ry;
@@ -557,12 +611,25 @@ static ws_status run_pass(ws_domain *d, StencilArgs &sa, int base, int out, bool
     so.eta = d->st[out][0];
     so.pout = d->st[out][1];
     so.qout = d->st[out][2];
-    so.pbase = d->st[base][1];
-    so.qbase = d->st[base][2];
+    so.pbase = d->st[a][1];
+    so.qbase = d->st[a][2];
     so.gh0 = d->ghost[0];
     so.gh1 = d->ghost[1];
     so.health = d->health;
-    so.sponge = sponge ? 1 : 0;
+    so.sponge = p == K ? 1 : 0;
+}
+
+static bool has_makers(const ws_domain *d) {
+    for (int q = 0; q < 4; ++q)
+        if (d->side_type[q] == WS_BC_WAVES) return true;
+    return false;
+}
+
+static ws_status run_pass(ws_domain *d, const StencilArgs &sa, const SolveArgs &so, hipStream_t st) {
+    {
+        ProfScope p(d, st, sa.kind == 2 ? WS_K_CORRECTOR : WS_K_PREDICTOR);
+        hipLaunchKernelGGL(k_stencil, strips(d), dim3(64 * SWG), 0, st, sa);
+    }
     {
         ProfScope p(d, st, WS_K_REDUCE);
         hipLaunchKernelGGL(k_reduce, tiles(d), dim3(NT), 0, st, so);
@@ -582,59 +649,29 @@ static ws_status run_pass(ws_domain *d, StencilArgs &sa, int base, int out, bool
 
 extern "C" ws_status ws_advance(ws_domain *d, int64_t nsteps, void *stream) {
     if (!d || nsteps < 0) return fail(WS_EINVAL, "ws_advance: bad argument");
+    if (d->batch) return fail(WS_EBUSY, "ws_advance: domain is attached to a batch (use ws_batch_advance)");
     hipStream_t st = (hipStream_t)stream;
     const Dom m = make_dom(d);
-    const ws_grid &g = d->g;
-    float x0 = 0.f, x1 = 0.f, x2 = 0.f;
-    if (g.fstar_extrap == 2) { x0 = 2.f; x1 = -3.f; x2 = 1.f; }
-    else if (g.fstar_extrap == 1) { x0 = 1.f; x1 = -1.f; }
+    const bool makers = has_makers(d);
     for (int64_t n = 0; n < nsteps; ++n) {
         const int64_t s = d->step + 1;
         const bool euler = s <= 2;
-        const int K = euler ? 0 : g.n_corr;
-        const int n0 = (int)((s - 1) % 3), n1 = (int)((s + 1) % 3), n2 = (int)(s % 3);
-        const double t0 = d->t, t1 = d->t + g.dt;
-        bool makers = false;
-        for (int q = 0; q < 4; ++q) makers |= d->side_type[q] == WS_BC_WAVES;
+        const int K = euler ? 0 : d->g.n_corr;
+        const double t0 = d->t, t1 = d->t + d->g.dt;
         if (makers) {
             const int n = 8 * d->gl;
             hipLaunchKernelGGL(k_ghosts, dim3((n + 255) / 256), dim3(256), 0, st, m, d->ghost[0], t0);
             hipLaunchKernelGGL(k_ghosts, dim3((n + 255) / 256), dim3(256), 0, st, m, d->ghost[1], t1);
         }
-        const int a = d->cur, b = (a + 1) % 3, c = (a + 2) % 3;  // base and the two estimates
         StencilArgs sa;
-        std::memset(&sa, 0, sizeof sa);
-        sa.d = m;
-        sa.ein = d->st[a][0]; sa.pin = d->st[a][1]; sa.qin = d->st[a][2];
-        sa.eout = d->st[b][0];
-        sa.rx = d->rx; sa.ry = d->ry;
-        sa.hE = d->hist[n0][0]; sa.hF = d->hist[n0][1]; sa.hG = d->hist[n0][2];
-        sa.hFs = d->hist[n0][3]; sa.hGs = d->hist[n0][4];
-        sa.E1 = d->hist[n1][0]; sa.F1 = d->hist[n1][1]; sa.G1 = d->hist[n1][2];
-        sa.Fs1 = d->hist[n1][3]; sa.Gs1 = d->hist[n1][4];
-        sa.E2 = d->hist[n2][0]; sa.F2 = d->hist[n2][1]; sa.G2 = d->hist[n2][2];
-        sa.Fs2 = d->hist[n2][3]; sa.Gs2 = d->hist[n2][4];
-        sa.Se = d->S[0]; sa.SU = d->S[1]; sa.SV = d->S[2];
-        sa.d.gh = d->ghost[0];
-        sa.dt = (float)g.dt;
-        sa.x0 = x0; sa.x1 = x1; sa.x2 = x2;
-        sa.kind = euler ? 0 : 1;
-        sa.write_S = (!euler && K > 0) ? 1 : 0;
-        ws_status r = run_pass(d, sa, a, b, K == 0, st);
-        if (r != WS_OK) return r;
-        int in = b;
-        for (int k = 1; k <= K; ++k) {
-            const int out = in == b ? c : b;
-            sa.ein = d->st[in][0]; sa.pin = d->st[in][1]; sa.qin = d->st[in][2];
-            sa.eout = d->st[out][0];
-            sa.d.gh = d->ghost[1];
-            sa.kind = 2;
-            sa.write_S = 0;
-            r = run_pass(d, sa, a, out, k == K, st);
+        SolveArgs so;
+        for (int p = 0; p <= K; ++p) {
+            pass_args(d, m, euler, d->cur, (int)(s % 3), p, sa, so);
+            ws_status r = run_pass(d, sa, so, st);
             if (r != WS_OK) return r;
-            in = out;
         }
-        d->cur = in;
+        const int b = (d->cur + 1) % 3, c = (d->cur + 2) % 3;
+        d->cur = K == 0 ? b : ((K & 1) ? c : b);
         d->step = s;
         d->t = t1;
     }
@@ -643,6 +680,7 @@ extern "C" ws_status ws_advance(ws_domain *d, int64_t nsteps, void *stream) {
 
 extern "C" ws_status ws_query(ws_domain *d, void *stream, int64_t *step, double *t, int32_t *health) {
     if (!d) return fail(WS_EINVAL, "ws_query: NULL domain");
+    if (busy_check(d, "ws_query") != WS_OK) return WS_EBUSY;
     hipStream_t st = (hipStream_t)stream;
     int h = 0;
     HIPCHK(hipStreamSynchronize(st));
@@ -652,4 +690,284 @@ extern "C" ws_status ws_query(ws_domain *d, void *stream, int64_t *step, double 
     if (health) *health = h;
     if (h) return fail(WS_ENONFINITE, "ws_query: non-finite state");
     return WS_OK;
+}
+
+// ------------------------------------------------------------------ batches
+struct ws_batch {
+    int max;
+    BatchDesc *d_desc;
+    BatchState *d_state;
+    int *d_pre[4];                       // prefix tables: stencil, tile, pcr, ghost workgroups
+    std::vector<ws_domain *> slots;      // attached domains by slot (nullptr = free)
+    std::vector<int> order;              // slots in device table order
+    std::vector<BatchState> h_state;     // host copy, device table order
+    bool dirty = true;                   // tables must be rebuilt and uploaded
+    bool stale = false;                  // device states ahead of the domains' host copies
+    int maxK = 0, nred = 0, total[4] = {0, 0, 0, 0};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t gstream = nullptr;
+    hipStream_t last = nullptr;
+};
+
+static size_t batch_layout(int max, size_t *o_state, size_t *o_pre) {
+    size_t a = align256(sizeof(BatchDesc) * (size_t)max);
+    size_t b = align256(sizeof(BatchState) * (size_t)max);
+    size_t c = align256(sizeof(int) * (size_t)(max + 1));
+    if (o_state) *o_state = a;
+    if (o_pre) *o_pre = a + b;
+    return a + b + 4 * c;
+}
+
+static void batch_touch(ws_domain *d) {
+    if (!d) return;
+    d->vdirty = true;
+    if (d->batch) d->batch->dirty = true;
+}
+
+static void batch_drop_graph(ws_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->gstream = nullptr;
+}
+
+static BatchDesc make_desc(const ws_domain *d) {
+    BatchDesc D;
+    std::memset(&D, 0, sizeof D);
+    D.d = make_dom(d);
+    D.sa = d->vsa;
+    D.so = d->vso;
+    D.ghost[0] = d->ghost[0];
+    D.ghost[1] = d->ghost[1];
+    D.dt = d->g.dt;
+    D.K = d->g.n_corr;
+    const dim3 sg = strips(d);
+    D.sgx = (int)sg.x;
+    D.sgy = (int)sg.y;
+    D.tgx = d->nxp / TX;
+    D.tgy = d->nyp / TY;
+    D.nsys = d->g.ny + d->g.nx;
+    D.makers = 0;
+    for (int q = 0; q < 4; ++q) D.makers += d->side_type[q] == WS_BC_WAVES;
+    return D;
+}
+
+// Pass argument tables of one domain (device), in the order of variant().
+static ws_status write_vtab(ws_domain *d) {
+    std::vector<StencilArgs> sa(d->nvar);
+    std::vector<SolveArgs> so(d->nvar);
+    const Dom m = make_dom(d);
+    for (int key = 0; key < 9; ++key) {
+        const int cur = key / 3, sm = key % 3;
+        pass_args(d, m, true, cur, sm, 0, sa[key], so[key]);
+        for (int p = 0; p <= d->g.n_corr; ++p) {
+            const int v = 9 + key * (d->g.n_corr + 1) + p;
+            pass_args(d, m, false, cur, sm, p, sa[v], so[v]);
+        }
+    }
+    HIPCHK(hipMemcpy(d->vsa, sa.data(), sizeof(StencilArgs) * d->nvar, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(d->vso, so.data(), sizeof(SolveArgs) * d->nvar, hipMemcpyHostToDevice));
+    d->vdirty = false;
+    return WS_OK;
+}
+
+// Device states -> the domains' host copies.
+static ws_status batch_pull(ws_batch *b, hipStream_t st) {
+    if (!b->stale) return WS_OK;
+    HIPCHK(hipStreamSynchronize(st));
+    const int n = (int)b->order.size();
+    if (n) HIPCHK(hipMemcpy(b->h_state.data(), b->d_state, sizeof(BatchState) * n, hipMemcpyDeviceToHost));
+    for (int k = 0; k < n; ++k) {
+        ws_domain *d = b->slots[b->order[k]];
+        d->step = b->h_state[k].step;
+        d->t = b->h_state[k].t;
+        d->cur = b->h_state[k].cur;
+        d->stale = false;
+    }
+    b->stale = false;
+    return WS_OK;
+}
+
+// Rebuild and upload descriptors, states and prefix tables from the domains
+// (whose host copies are current: callers pull first).  The captured step
+// stays valid unless the launch shapes changed.
+static ws_status batch_upload(ws_batch *b) {
+    if (batch_pull(b, b->last) != WS_OK) return WS_EHIP;
+    std::vector<int> order;
+    for (int sl = 0; sl < b->max; ++sl)
+        if (b->slots[sl]) order.push_back(sl);
+    const int n = (int)order.size();
+    std::vector<BatchDesc> desc(n);
+    b->h_state.assign(n, BatchState());
+    std::vector<int> pre[4];
+    for (int q = 0; q < 4; ++q) pre[q].assign(n + 1, 0);
+    int maxK = 0, nred = 0;
+    for (int k = 0; k < n; ++k) {
+        ws_domain *d = b->slots[order[k]];
+        if (d->vdirty) {
+            ws_status r = write_vtab(d);
+            if (r != WS_OK) return r;
+        }
+        d->bidx = k;
+        desc[k] = make_desc(d);
+        b->h_state[k].step = d->step;
+        b->h_state[k].t = d->t;
+        b->h_state[k].cur = d->cur;
+        b->h_state[k].pad = 0;
+        const BatchDesc &D = desc[k];
+        pre[0][k + 1] = pre[0][k] + D.sgx * D.sgy;
+        pre[1][k + 1] = pre[1][k] + D.tgx * D.tgy;
+        pre[2][k + 1] = pre[2][k] + D.nsys;
+        pre[3][k + 1] = pre[3][k] + (D.makers ? (8 * D.d.gl + 255) / 256 : 0);
+        maxK = D.K > maxK ? D.K : maxK;
+        const int nr = d->nu > d->nv ? d->nu : d->nv;
+        nred = nr > nred ? nr : nred;
+    }
+    if (n) {
+        HIPCHK(hipMemcpy(b->d_desc, desc.data(), sizeof(BatchDesc) * n, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(b->d_state, b->h_state.data(), sizeof(BatchState) * n, hipMemcpyHostToDevice));
+        for (int q = 0; q < 4; ++q)
+            HIPCHK(hipMemcpy(b->d_pre[q], pre[q].data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice));
+    }
+    bool same = n == (int)b->order.size() && maxK == b->maxK && nred == b->nred;
+    for (int q = 0; q < 4; ++q) same = same && pre[q][n] == b->total[q];
+    if (!same) batch_drop_graph(b);
+    b->order = order;
+    b->maxK = maxK;
+    b->nred = nred;
+    for (int q = 0; q < 4; ++q) b->total[q] = pre[q][n];
+    b->dirty = false;
+    return WS_OK;
+}
+
+// The launches of one step for every domain of the batch.
+static ws_status batch_step(ws_batch *b, hipStream_t st) {
+    const int n = (int)b->order.size();
+    if (b->total[3] > 0) {
+        hipLaunchKernelGGL(kb_ghosts, dim3(b->total[3]), dim3(256), 0, st, b->d_desc, b->d_state, b->d_pre[3], n, 0);
+        hipLaunchKernelGGL(kb_ghosts, dim3(b->total[3]), dim3(256), 0, st, b->d_desc, b->d_state, b->d_pre[3], n, 1);
+    }
+    for (int p = 0; p <= b->maxK; ++p) {
+        hipLaunchKernelGGL(kb_stencil, dim3(b->total[0]), dim3(64 * SWG), 0, st, b->d_desc, b->d_state, b->d_pre[0], n, p);
+        hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NT), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, p);
+        hipLaunchKernelGGL(kb_pcr, dim3(b->total[2]), dim3(PCR_NT), sizeof(float4) * b->nred, st, b->d_desc,
+                           b->d_state, b->d_pre[2], n, p);
+        hipLaunchKernelGGL(kb_expand, dim3(b->total[1]), dim3(NT), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, p);
+    }
+    hipLaunchKernelGGL(kb_finish, dim3((n + 255) / 256), dim3(256), 0, st, b->d_desc, b->d_state, n);
+    HIPCHK(hipGetLastError());
+    return WS_OK;
+}
+
+extern "C" size_t ws_batch_workspace_bytes(int32_t max_domains) {
+    if (max_domains < 1) return 0;
+    return batch_layout(max_domains, nullptr, nullptr);
+}
+
+extern "C" ws_status ws_batch_create(int32_t max_domains, void *workspace_dev, size_t bytes, ws_batch **out) {
+    if (!out || max_domains < 1 || !workspace_dev) return fail(WS_EINVAL, "ws_batch_create: bad argument");
+    if (((uintptr_t)workspace_dev & 255) != 0) return fail(WS_EINVAL, "ws_batch_create: workspace not 256-byte aligned");
+    size_t o_state, o_pre;
+    const size_t need = batch_layout(max_domains, &o_state, &o_pre);
+    if (bytes < need) return fail(WS_ENOMEM, "ws_batch_create: workspace %zu < %zu bytes", bytes, need);
+    ws_batch *b = new (std::nothrow) ws_batch();
+    if (!b) return fail(WS_ENOMEM, "ws_batch_create: host allocation failed");
+    char *base = (char *)workspace_dev;
+    b->max = max_domains;
+    b->d_desc = (BatchDesc *)base;
+    b->d_state = (BatchState *)(base + o_state);
+    const size_t c = align256(sizeof(int) * (size_t)(max_domains + 1));
+    for (int q = 0; q < 4; ++q) b->d_pre[q] = (int *)(base + o_pre + q * c);
+    b->slots.assign(max_domains, nullptr);
+    *out = b;
+    return WS_OK;
+}
+
+extern "C" ws_status ws_batch_destroy(ws_batch *b) {
+    if (!b) return WS_OK;
+    if (b->last) (void)hipStreamSynchronize(b->last);
+    (void)batch_pull(b, b->last);
+    for (ws_domain *d : b->slots)
+        if (d) {
+            d->batch = nullptr;
+            d->stale = false;
+        }
+    batch_drop_graph(b);
+    delete b;
+    return WS_OK;
+}
+
+extern "C" ws_status ws_batch_attach(ws_batch *b, ws_domain *d, int32_t *slot) {
+    if (!b || !d) return fail(WS_EINVAL, "ws_batch_attach: bad argument");
+    if (d->batch) return fail(WS_EBUSY, "ws_batch_attach: domain already attached");
+    if (batch_pull(b, b->last) != WS_OK) return WS_EHIP;
+    for (int sl = 0; sl < b->max; ++sl)
+        if (!b->slots[sl]) {
+            b->slots[sl] = d;
+            d->batch = b;
+            d->stale = false;
+            b->dirty = true;
+            if (slot) *slot = sl;
+            return WS_OK;
+        }
+    return fail(WS_EBUSY, "ws_batch_attach: batch full (%d domains)", b->max);
+}
+
+extern "C" ws_status ws_batch_detach(ws_batch *b, int32_t slot) {
+    if (!b || slot < 0 || slot >= b->max || !b->slots[slot]) return fail(WS_EINVAL, "ws_batch_detach: bad slot");
+    if (batch_pull(b, b->last) != WS_OK) return WS_EHIP;
+    ws_domain *d = b->slots[slot];
+    d->batch = nullptr;
+    d->stale = false;
+    b->slots[slot] = nullptr;
+    b->dirty = true;
+    return WS_OK;
+}
+
+extern "C" ws_status ws_batch_advance(ws_batch *b, int64_t nsteps, void *stream) {
+    if (!b || nsteps < 0) return fail(WS_EINVAL, "ws_batch_advance: bad argument");
+    hipStream_t st = (hipStream_t)stream;
+    if (b->stale && b->last != st) {
+        ws_status r = batch_pull(b, b->last);
+        if (r != WS_OK) return r;
+    }
+    if (b->dirty) {
+        if (b->last) HIPCHK(hipStreamSynchronize(b->last));
+        ws_status r = batch_upload(b);
+        if (r != WS_OK) return r;
+    }
+    if (b->order.empty() || nsteps == 0) return WS_OK;
+    b->last = st;
+    if (st != nullptr && (!b->exec || b->gstream != st)) {
+        batch_drop_graph(b);
+        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+        ws_status r = batch_step(b, st);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(st, &g);
+        if (r != WS_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return r;
+        }
+        if (e != hipSuccess) return fail(WS_EHIP, "ws_batch_advance: graph capture failed: %s", hipGetErrorString(e));
+        b->graph = g;
+        HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        b->gstream = st;
+    }
+    for (int64_t k = 0; k < nsteps; ++k) {
+        if (b->exec) HIPCHK(hipGraphLaunch(b->exec, st));
+        else {
+            ws_status r = batch_step(b, st);
+            if (r != WS_OK) return r;
+        }
+    }
+    b->stale = true;
+    for (int sl : b->order) b->slots[sl]->stale = true;
+    return WS_OK;
+}
+
+extern "C" ws_status ws_batch_sync(ws_batch *b, void *stream) {
+    if (!b) return fail(WS_EINVAL, "ws_batch_sync: NULL batch");
+    return batch_pull(b, (hipStream_t)stream);
 }

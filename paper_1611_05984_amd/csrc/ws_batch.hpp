@@ -1,0 +1,163 @@
+// ws_batch.hpp -- many independent domains advanced together.
+//
+// Every attached domain has a static descriptor (its grid, launch geometry
+// and a table of the argument blocks of every pass variant) and a small
+// device-side state (completed steps, time, current state buffer).  The pass
+// bookkeeping that the single-domain path does on the host (Euler start-up,
+// history slots, buffer rotation, ghost time level, sponge on the last pass)
+// reduces to picking a table entry from that state on the device, so the
+// launches of one step are identical from step to step and the step can be
+// captured once in a hipGraph and replayed.  A workgroup copies its argument
+// block from global memory before its first store (uniform addresses, so the
+// copy is scalar loads into SGPRs, as for the single-domain kernels' own
+// kernel-argument segment).  Each phase of a pass
+// is one launch for all domains: workgroup b finds its domain by binary
+// search in a prefix table of per-domain workgroup counts; domains still in
+// their Euler start-up skip the corrector passes.  A last tiny kernel
+// advances every domain's state.
+#pragma once
+#include "ws_kernels.hpp"
+
+namespace ws {
+
+struct BatchDesc {
+    Dom d;                     // grid, depth, sides (wave-maker ghosts)
+    const StencilArgs *sa;     // per-variant pass arguments (see variant())
+    const SolveArgs *so;
+    float *ghost[2];
+    double dt;
+    int K;                     // corrector passes of a full (AB3) step
+    int sgx, sgy;              // stencil workgroup grid
+    int tgx, tgy;              // solver tile grid
+    int nsys;                  // reduced systems: ny + nx
+    int makers;                // number of wave-maker sides
+    int pad;
+};
+
+struct BatchState {
+    long long step;            // completed steps since (re)start
+    double t;
+    int cur;                   // state buffer of the current state
+    int pad;
+};
+
+// Argument-table entry of pass p of the step a domain takes next, or -1 when
+// the domain has no such pass (correctors of the Euler start-up steps).
+// Entries 0..8: Euler steps by (state buffer, step mod 3); then full steps by
+// (state buffer, step mod 3, pass).
+__device__ __forceinline__ int variant(const BatchDesc &D, const BatchState &S, int p) {
+    const long long s = S.step + 1;
+    const int sm = (int)(s % 3), key = S.cur * 3 + sm;
+    if (s <= 2) return p == 0 ? key : -1;
+    return p <= D.K ? 9 + key * (D.K + 1) + p : -1;
+}
+
+// Copy of a block of kernel parameters held in global memory, read through the
+// constant address space: workgroup-uniform scalar loads into SGPRs (valid
+// only for memory no kernel of the launch writes).
+template <class T> __device__ __forceinline__ T load_params(const T *p) {
+    static_assert(sizeof(T) % 4 == 0, "parameter blocks are whole dwords");
+    T r;
+    const __attribute__((address_space(4))) unsigned *src = (const __attribute__((address_space(4))) unsigned *)p;
+    unsigned *dst = reinterpret_cast<unsigned *>(&r);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = src[i];
+    return r;
+}
+
+__device__ __forceinline__ int find_dom(const int *prefix, int ndom, int b) {
+    int lo = 0, hi = ndom;  // prefix[lo] <= b < prefix[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(64 * SWG) void kb_stencil(const BatchDesc *__restrict__ descs,
+                                                       const BatchState *__restrict__ states,
+                                                       const int *__restrict__ prefix, int ndom, int p) {
+    const int b = blockIdx.x, dm = find_dom(prefix, ndom, b);
+    const BatchDesc &D = descs[dm];
+    const int v = variant(D, states[dm], p);
+    if (v < 0) return;
+    const int local = b - prefix[dm];
+    const StencilArgs A = load_params(D.sa + v);
+    stencil_body(A, local % D.sgx, local / D.sgx);
+}
+
+__global__ __launch_bounds__(NT) void kb_reduce(const BatchDesc *__restrict__ descs,
+                                                const BatchState *__restrict__ states,
+                                                const int *__restrict__ prefix, int ndom, int p) {
+    __shared__ SolveTile s;
+    const int b = blockIdx.x, dm = find_dom(prefix, ndom, b);
+    const BatchDesc &D = descs[dm];
+    const int v = variant(D, states[dm], p);
+    if (v < 0) return;
+    const int local = b - prefix[dm];
+    const SolveArgs A = load_params(D.so + v);
+    reduce_body(A, s, local % D.tgx, local / D.tgx);
+}
+
+__global__ __launch_bounds__(PCR_NT) void kb_pcr(const BatchDesc *__restrict__ descs,
+                                                 const BatchState *__restrict__ states,
+                                                 const int *__restrict__ prefix, int ndom, int p) {
+    extern __shared__ float4 buf[];
+    const int b = blockIdx.x, dm = find_dom(prefix, ndom, b);
+    const BatchDesc &D = descs[dm];
+    const int v = variant(D, states[dm], p);
+    if (v < 0) return;
+    const SolveArgs *g = D.so + v;  // only the fields the solve needs
+    const int sys = b - prefix[dm], ny = load_params(&g->d.ny);
+    if (sys < ny) {
+        const int N = load_params(&g->d.nu);
+        pcr_solve(N, load_params(&g->redx) + (size_t)sys * N, load_params(&g->solx) + (size_t)sys * N, buf);
+    } else {
+        const int N = load_params(&g->d.nv);
+        pcr_solve(N, load_params(&g->redy) + (size_t)(sys - ny) * N, load_params(&g->soly) + (size_t)(sys - ny) * N,
+                  buf);
+    }
+}
+
+__global__ __launch_bounds__(NT) void kb_expand(const BatchDesc *__restrict__ descs,
+                                                const BatchState *__restrict__ states,
+                                                const int *__restrict__ prefix, int ndom, int p) {
+    __shared__ SolveTile s;
+    const int b = blockIdx.x, dm = find_dom(prefix, ndom, b);
+    const BatchDesc &D = descs[dm];
+    const int v = variant(D, states[dm], p);
+    if (v < 0) return;
+    const int local = b - prefix[dm];
+    const SolveArgs A = load_params(D.so + v);
+    expand_body(A, s, local % D.tgx, local / D.tgx);
+}
+
+// Wave-maker ghosts of t^n (which = 0) and t^{n+1} (which = 1); 256 threads
+// per block, 8 gl threads per domain with wave makers.
+__global__ void kb_ghosts(const BatchDesc *descs, const BatchState *states, const int *prefix, int ndom,
+                          int which) {
+    const int b = blockIdx.x, dm = find_dom(prefix, ndom, b);
+    const BatchDesc &D = descs[dm];
+    if (!D.makers) return;
+    const int k = (b - prefix[dm]) * blockDim.x + threadIdx.x;
+    if (k >= 8 * D.d.gl) return;
+    const double t = states[dm].t + (which ? D.dt : 0.0);
+    ghosts_body(D.d, D.ghost[which], t, k);
+}
+
+// Completes the step of every domain: buffer of the final estimate, step, time.
+__global__ void kb_finish(const BatchDesc *descs, BatchState *states, int ndom) {
+    const int dm = blockIdx.x * blockDim.x + threadIdx.x;
+    if (dm >= ndom) return;
+    BatchState S = states[dm];
+    const long long s = S.step + 1;
+    const int K = s <= 2 ? 0 : descs[dm].K;
+    const int b = (S.cur + 1) % 3, c = (S.cur + 2) % 3;
+    S.cur = K == 0 ? b : ((K & 1) ? c : b);
+    S.step = s;
+    S.t = S.t + descs[dm].dt;
+    states[dm] = S;
+}
+
+}  // namespace ws

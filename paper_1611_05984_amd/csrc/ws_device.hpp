@@ -51,6 +51,12 @@ __device__ __forceinline__ size_t ghost_index(const Dom &d, int side, int layer,
 
 __device__ __forceinline__ bool is_wall(const Dom &d, int s) { return d.side[s].type != BC_WAVES; }
 
+// Side type by a run-time side index, as selects: keeps a Dom held in
+// registers free of dynamic indexing.
+__device__ __forceinline__ int side_type(const Dom &d, int s) {
+    return s == 0 ? d.side[0].type : s == 1 ? d.side[1].type : s == 2 ? d.side[2].type : d.side[3].type;
+}
+
 // Corner index behind a side: mirrored across walls and sponges, held at the
 // boundary value across wave makers; clamped into range for padding cells.
 __device__ __forceinline__ int map_corner(int c, int n, bool lo_wall, bool hi_wall) {
@@ -102,7 +108,7 @@ __device__ inline void load_cell(const Dom &d, const float *__restrict__ E,
     int side = -1;
     if (!in_i) side = i < 0 ? 0 : 1;
     else if (!in_j) side = j < 0 ? 2 : 3;
-    if (side >= 0 && d.side[side].type == BC_WAVES) {
+    if (side >= 0 && side_type(d, side) == BC_WAVES) {
         int layer = side == 0 ? -1 - i : side == 1 ? i - d.nx : side == 2 ? -1 - j : j - d.ny;
         int pos = (side < 2 ? j : i) + 2;
         layer = layer < 0 ? 0 : (layer > 1 ? 1 : layer);

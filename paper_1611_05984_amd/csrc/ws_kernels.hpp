@@ -45,8 +45,7 @@ __device__ __forceinline__ float dcell4(float a, float b, float c, float d) {
 }
 
 // Ghost values of every wave-maker side at time t (eqs. 25-28 per component).
-__global__ void k_ghosts(Dom d, float *gh, double t) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void ghosts_body(const Dom &d, float *gh, double t, int k) {
     const int pos = k % d.gl, layer = (k / d.gl) % 2, side = k / (2 * d.gl);
     if (side >= 4 || d.side[side].type != BC_WAVES) return;
     int i, j;
@@ -65,16 +64,18 @@ __global__ void k_ghosts(Dom d, float *gh, double t) {
     o[2] = q;
 }
 
-__global__ __launch_bounds__(64 * SWG) void k_stencil(StencilArgs A) {
+__global__ void k_ghosts(Dom d, float *gh, double t) { ghosts_body(d, gh, t, blockIdx.x * blockDim.x + threadIdx.x); }
+
+__device__ __forceinline__ void stencil_body(const StencilArgs &A, int bx, int by) {
     const Dom &d = A.d;
     const int lane = threadIdx.x & 63;
-    const int strip = blockIdx.x * SWG + (threadIdx.x >> 6);
+    const int strip = bx * SWG + (threadIdx.x >> 6);
     const int c0 = strip * SO - 1;  // column of lane 0; lanes 1..62 are output columns
     if (c0 + 1 >= d.nx) return;     // whole wave past the domain
     const int col = c0 + lane;
     const int hcol = lane == 0 ? c0 - 1 : c0 + 64;  // halo column held by lanes 0 and 63
     const bool halo_lane = lane == 0 || lane == 63;
-    const int j0 = blockIdx.y * SY;
+    const int j0 = by * SY;
     const float th = d.theta, g = d.g, eps = d.eps;
     const float rdx = d.rdx, rdy = d.rdy, Bd = d.Bd, B3 = d.Bd + 1.f / 3.f;
     // strips whose cells and corners (with halo) all lie inside the domain
@@ -250,6 +251,8 @@ __global__ __launch_bounds__(64 * SWG) void k_stencil(StencilArgs A) {
     }
 }
 
+__global__ __launch_bounds__(64 * SWG) void k_stencil(StencilArgs A) { stencil_body(A, blockIdx.x, blockIdx.y); }
+
 // ------------------------------------------------------------- solver parts
 struct SolveArgs {
     Dom d;
@@ -405,10 +408,9 @@ __device__ __forceinline__ void seg_expand(float *r, int st, float (&a)[M], floa
 
 // Wave 0 owns the 64 row segments of a tile (lane -> segment lane/16 of row
 // lane%16, conflict-free with the padded rows), wave 1 its 64 column segments.
-__global__ __launch_bounds__(NT) void k_reduce(SolveArgs A) {
-    __shared__ SolveTile s;
+__device__ __forceinline__ void reduce_body(const SolveArgs &A, SolveTile &s, int bx, int by) {
     const Dom &d = A.d;
-    const int tid = threadIdx.x, bx = blockIdx.x, by = blockIdx.y;
+    const int tid = threadIdx.x;
     const int i0 = bx * TX, j0 = by * TY;
     for (int k = tid; k < TX * TY; k += NT) {
         const int cx = k % TX, cy = k / TX;
@@ -447,28 +449,19 @@ __global__ __launch_bounds__(NT) void k_reduce(SolveArgs A) {
     }
 }
 
+__global__ __launch_bounds__(NT) void k_reduce(SolveArgs A) {
+    __shared__ SolveTile s;
+    reduce_body(A, s, blockIdx.x, blockIdx.y);
+}
+
 // Parallel cyclic reduction of one reduced system (rows first, then
 // columns): each thread keeps its equations (k = tid + j * PCR_NT) in
 // registers; one LDS copy of the system (dynamic size N) is read, then
 // overwritten, per reduction level.
 constexpr int PCR_NT = 128;
 constexpr int PCR_EPL = NRED_MAX / PCR_NT;  // equations per thread at most
-__global__ __launch_bounds__(PCR_NT) void k_pcr(SolveArgs A) {
-    extern __shared__ float4 buf[];
-    const Dom &d = A.d;
-    int sys = blockIdx.x, N;
-    const float4 *src;
-    float *dst;
-    if (sys < d.ny) {
-        N = d.nu;
-        src = A.redx + (size_t)sys * N;
-        dst = A.solx + (size_t)sys * N;
-    } else {
-        sys -= d.ny;
-        N = d.nv;
-        src = A.redy + (size_t)sys * N;
-        dst = A.soly + (size_t)sys * N;
-    }
+// One reduced system of N equations (sub, diag, super, rhs) from src; solutions to dst.
+__device__ __forceinline__ void pcr_solve(int N, const float4 *src, float *dst, float4 *buf) {
     const int tid = threadIdx.x;
     const int nmine = (N - tid + PCR_NT - 1) / PCR_NT;
     float4 eq[PCR_EPL];
@@ -502,10 +495,21 @@ __global__ __launch_bounds__(PCR_NT) void k_pcr(SolveArgs A) {
         if (j < nmine) dst[tid + j * PCR_NT] = eq[j].w / eq[j].y;
 }
 
-__global__ __launch_bounds__(NT) void k_expand(SolveArgs A) {
-    __shared__ SolveTile s;
+// System sys: rows 0..ny-1 (x direction), then columns.
+__device__ __forceinline__ void pcr_body(const SolveArgs &A, float4 *buf, int sys) {
     const Dom &d = A.d;
-    const int tid = threadIdx.x, bx = blockIdx.x, by = blockIdx.y;
+    if (sys < d.ny) pcr_solve(d.nu, A.redx + (size_t)sys * d.nu, A.solx + (size_t)sys * d.nu, buf);
+    else pcr_solve(d.nv, A.redy + (size_t)(sys - d.ny) * d.nv, A.soly + (size_t)(sys - d.ny) * d.nv, buf);
+}
+
+__global__ __launch_bounds__(PCR_NT) void k_pcr(SolveArgs A) {
+    extern __shared__ float4 buf[];
+    pcr_body(A, buf, blockIdx.x);
+}
+
+__device__ __forceinline__ void expand_body(const SolveArgs &A, SolveTile &s, int bx, int by) {
+    const Dom &d = A.d;
+    const int tid = threadIdx.x;
     const int i0 = bx * TX, j0 = by * TY;
     for (int k = tid; k < TX * TY; k += NT) {
         const int cx = k % TX, cy = k / TX;
@@ -571,6 +575,11 @@ __global__ __launch_bounds__(NT) void k_expand(SolveArgs A) {
         A.qout[o] = Q;
     }
     if (bad) atomicOr(A.health, 1);
+}
+
+__global__ __launch_bounds__(NT) void k_expand(SolveArgs A) {
+    __shared__ SolveTile s;
+    expand_body(A, s, blockIdx.x, blockIdx.y);
 }
 
 }  // namespace ws

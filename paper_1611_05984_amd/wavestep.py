@@ -75,6 +75,13 @@ def lib():
             "ws_last_error": (C.c_char_p, []),
             "ws_profile_enable": (C.c_int, [vp, i32]),
             "ws_profile_collect": (C.c_int, [vp, vp, C.POINTER(f64), C.POINTER(i64), i32]),
+            "ws_batch_workspace_bytes": (sz, [i32]),
+            "ws_batch_create": (C.c_int, [i32, vp, sz, C.POINTER(vp)]),
+            "ws_batch_destroy": (C.c_int, [vp]),
+            "ws_batch_attach": (C.c_int, [vp, vp, C.POINTER(i32)]),
+            "ws_batch_detach": (C.c_int, [vp, i32]),
+            "ws_batch_advance": (C.c_int, [vp, i64, vp]),
+            "ws_batch_sync": (C.c_int, [vp, vp]),
         }
         for name, (res, args) in sigs.items():
             fn = getattr(L, name)
@@ -211,3 +218,60 @@ class Domain:
         n = (C.c_int64 * K_COUNT)()
         _check(lib().ws_profile_collect(self._h, _stream(stream), ms, n, K_COUNT), "ws_profile_collect")
         return {KERNEL_NAMES[k]: (ms[k], n[k]) for k in range(K_COUNT)}
+
+
+class Batch:
+    """Many domains advanced together: one launch per phase for all of them,
+    one step captured as a HIP graph on the batch's own stream and replayed.
+
+    Attached domains are advanced only through the batch; after ``advance``
+    call ``sync`` before using them individually (read, query, edits, ...).
+    Work the caller queued on its current stream before ``advance`` (states,
+    edits) is ordered before the batch's steps.
+    """
+
+    def __init__(self, max_domains, device="cuda"):
+        import torch
+        self.device = torch.device(device)
+        self.max = int(max_domains)
+        nbytes = int(lib().ws_batch_workspace_bytes(self.max))
+        if nbytes == 0:
+            raise WaveStepError(EINVAL, "invalid batch size")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.Stream(device=self.device)   # default priority
+        h = C.c_void_p()
+        _check(lib().ws_batch_create(self.max, _dptr(self.workspace), nbytes, C.byref(h)),
+               "ws_batch_create")
+        self._h = h
+        self.domains = {}
+
+    def attach(self, dom: Domain) -> int:
+        slot = C.c_int32()
+        _check(lib().ws_batch_attach(self._h, dom._h, C.byref(slot)), "ws_batch_attach")
+        self.domains[slot.value] = dom
+        return slot.value
+
+    def detach(self, slot: int):
+        _check(lib().ws_batch_detach(self._h, int(slot)), "ws_batch_detach")
+        return self.domains.pop(int(slot))
+
+    def advance(self, n):
+        import torch
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        _check(lib().ws_batch_advance(self._h, int(n), C.c_void_p(self.stream.cuda_stream)),
+               "ws_batch_advance")
+
+    def sync(self):
+        _check(lib().ws_batch_sync(self._h, C.c_void_p(self.stream.cuda_stream)), "ws_batch_sync")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ws_batch_destroy(self._h)
+            self._h = None
+            self.domains = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,192 @@
+"""Batched stepping (many independent domains, one launch per phase for all
+of them, the step replayed as a HIP graph) through the C ABI.
+
+The batched kernels run the same per-cell arithmetic as the single-domain
+kernels, so a domain advanced in a batch must equal, bit for bit, the same
+domain advanced alone (which the single-domain parity tests tie to the FP64
+oracle); a few batched domains are also compared with the oracle directly.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as o
+from paper_1611_05984_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+G = 9.81
+
+
+def _ws():
+    from paper_1611_05984_amd import wavestep as ws
+    return ws
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def make(w, **params):
+    ws = _ws()
+    z = w.z.astype(np.float32).astype(np.float64)
+    d = ws.Domain(w.nx, w.ny, w.dx, w.dy, w.dt, z, **params)
+    for s, side in enumerate(w.sides):
+        if side.kind != wl.SOLID:
+            d.set_boundary(s, side.kind, side.width, side.amp, side.period, side.theta,
+                           side.phase or None)
+    for (H, th, x0, y0) in w.solitary:
+        d.add_solitary(H, th, x0, y0)
+    return d
+
+
+def mixed_cases():
+    """Uneven ensemble members plus domains with wave makers, sponges and other
+    corrector counts / models, so one batch mixes every pass count."""
+    cases = [(w, {}) for w in wl.config4(n_domains=5, lo=64, hi=200, seed=41)]
+    c2 = wl.config2(nx=200, ny=72, seed=7)
+    cases.append((c2, {}))
+    cases.append((c2, {"n_corr": 1}))
+    cases.append((wl.config1(nx=130, ny=40), {"n_corr": 3}))
+    cases.append((wl.config1(nx=96, ny=66), {"model": 1}))
+    cases.append((wl.config1(nx=70, ny=70), {"n_corr": 0}))
+    return cases
+
+
+def same(a, b, what):
+    ae, aP, aQ = a.state_numpy()
+    be, bP, bQ = b.state_numpy()
+    for x, y, f in ((ae, be, "w"), (aP, bP, "P"), (aQ, bQ, "Q")):
+        if not np.array_equal(x, y):
+            k = np.unravel_index(np.argmax(np.abs(x - y)), x.shape)
+            raise AssertionError("%s %s differs: max |d| = %.3e at %s" % (what, f, np.abs(x - y).max(), k))
+    sa, sb = a.query(), b.query()
+    assert sa[0] == sb[0] and sa[1] == sb[1] and sa[2] == 0 and sb[2] == 0, (what, sa, sb)
+
+
+def test_batch_equals_single_domains_bitwise():
+    ws = _ws()
+    cases = mixed_cases()
+    say("case: batch of %d mixed domains vs the same domains alone" % len(cases))
+    alone = [make(w, **p) for w, p in cases]
+    inb = [make(w, **p) for w, p in cases]
+    for k, (a, b) in enumerate(zip(alone, inb)):   # mixed step indices, Euler start-ups in the batch
+        a.advance(k % 4)
+        b.advance(k % 4)
+    B = ws.Batch(16)
+    for b in inb:
+        B.attach(b)
+    done = 0
+    for chunk in (1, 1, 3, 7, 20):
+        B.advance(chunk)
+        for a in alone:
+            a.advance(chunk)
+        done += chunk
+        B.sync()
+        say("  after %d batched steps" % done)
+        for k, (a, b) in enumerate(zip(alone, inb)):
+            same(a, b, "domain %d (%s)" % (k, cases[k][0].name))
+    B.close()
+
+
+def test_batch_edits_attach_detach_and_busy():
+    ws = _ws()
+    cases = [(w, {}) for w in wl.config4(n_domains=4, lo=80, hi=160, seed=42)]
+    say("case: batch edits / detach / attach, %d domains" % len(cases))
+    alone = [make(w, **p) for w, p in cases]
+    inb = [make(w, **p) for w, p in cases]
+    B = ws.Batch(4)
+    slots = [B.attach(b) for b in inb[:3]]
+    B.advance(10)
+    for a in alone[:3]:
+        a.advance(10)
+    with pytest.raises(ws.WaveStepError) as e:       # stale until synced
+        inb[0].read()
+    assert e.value.status == ws.EBUSY
+    B.sync()
+    with pytest.raises(ws.WaveStepError) as e:       # attached: advanced only by the batch
+        inb[0].advance(1)
+    assert e.value.status == ws.EBUSY
+    w0, w1 = cases[0][0], cases[1][0]
+    for d in (alone[0], inb[0]):
+        assert d.apply_edit(ws.EDIT_WATER, 0.4 * w0.nx * w0.dx, 0.5 * w0.ny * w0.dy, 0.2, 4 * w0.dx) == 0
+    for d in (alone[1], inb[1]):
+        assert d.apply_edit(ws.EDIT_TERRAIN, 0.85 * w1.nx * w1.dx, 0.3 * w1.ny * w1.dy, 0.3,
+                            6 * w1.dx) == 0
+    B.advance(5)
+    for a in alone[:3]:
+        a.advance(5)
+    B.sync()
+    B.detach(slots[2])
+    inb[2].advance(4)                               # usable alone again
+    alone[2].advance(4)
+    alone[3].advance(2)
+    inb[3].advance(2)
+    B.attach(inb[3])
+    for step in range(3):                           # repeated graph replays with eager work between
+        B.advance(4)
+        for k in (0, 1, 3):
+            alone[k].advance(4)
+        B.sync()
+        for k in (0, 1, 3):
+            same(alone[k], inb[k], "domain %d replay %d" % (k, step))
+    same(alone[2], inb[2], "detached domain")
+    B.close()
+
+
+def test_batch_vs_oracle():
+    ws = _ws()
+    cases = wl.config4(n_domains=3, lo=96, hi=144, seed=43)
+    say("case: batched config-4 members vs oracle, 60 steps")
+    gpus = [make(w) for w in cases]
+    oras = []
+    for w in cases:
+        z = w.z.astype(np.float32).astype(np.float64)
+        d = o.Domain(w.nx, w.ny, w.dx, w.dy, w.dt, z)
+        for (H, th, x0, y0) in w.solitary:
+            d.add_solitary(H, th, x0, y0)
+        oras.append(d)
+    B = ws.Batch(3)
+    for g in gpus:
+        B.attach(g)
+    B.advance(60)
+    for d in oras:
+        d.advance(60)
+    B.sync()
+    for w, g, d in zip(cases, gpus, oras):
+        H = w.solitary[0][0]
+        ge, gP, gQ = g.state_numpy()
+        oe, oP, oQ = d.state()
+        de, dP, dQ = np.abs(ge - oe).max(), np.abs(gP - oP).max(), np.abs(gQ - oQ).max()
+        say("  %s: max|d eta| %.3e  |dP| %.3e  |dQ| %.3e (H %.3f)" % (w.name, de, dP, dQ, H))
+        assert de <= 1e-4 * H and max(dP, dQ) <= 1e-4 * H * math.sqrt(G * 1.0), w.name
+        assert g.query()[0] == d.step
+    B.close()
+
+
+def test_config4_full_size_batch_sampled_vs_alone():
+    """The full 256-domain ensemble (nx, ny ~ U{256..1024}) as the benchmark
+    runs it: every domain stays finite, and the smallest, the largest and a
+    beach domain equal their single-domain runs bit for bit."""
+    ws = _ws()
+    ens = wl.config4()
+    say("case: config4 full size, %d domains, %.3g cells" % (len(ens), sum(w.cells for w in ens)))
+    doms = [make(w) for w in ens]
+    cells = [w.cells for w in ens]
+    pick = sorted({int(np.argmin(cells)), int(np.argmax(cells)),
+                   next(k for k, w in enumerate(ens) if w.z.max() > -0.99)})
+    alone = {k: make(ens[k]) for k in pick}
+    B = ws.Batch(len(ens))
+    for d in doms:
+        B.attach(d)
+    B.advance(12)
+    for k in pick:
+        alone[k].advance(12)
+    B.sync()
+    for k in pick:
+        same(alone[k], doms[k], "ensemble domain %d (%s)" % (k, ens[k].name))
+    bad = [k for k, d in enumerate(doms) if d.query()[2] != 0]
+    assert not bad, bad
+    B.close()
