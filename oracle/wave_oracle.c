@@ -861,9 +861,16 @@ int or_apply_edit(or_domain *D, int kind, double x0, double y0, double amp, doub
                 D->w[CI(D, i, j)] += amp * exp(-(x * x + y * y) / (2.0 * sigma * sigma));
             }
     } else {
+        /* Terrain change under water keeps the free surface and the
+         * depth-averaged velocity (momentum scales with the remaining depth,
+         * never up); the paper leaves the state's treatment open. */
         size_t nz = (size_t)(D->p.nx + 5) * (D->p.ny + 5);
+        size_t nc = (size_t)D->p.nx * D->p.ny;
         double *save = malloc(nz * sizeof(double));
+        double *hold = malloc(nc * sizeof(double));
         memcpy(save, D->z, nz * sizeof(double));
+        for (int j = 0; j < D->p.ny; ++j)
+            for (int i = 0; i < D->p.nx; ++i) hold[(size_t)j * D->p.nx + i] = D->w[CI(D, i, j)] - bcell(D, i, j);
         for (int cj = 0; cj <= D->p.ny; ++cj)
             for (int ci = 0; ci <= D->p.nx; ++ci) {
                 double x = ci * D->p.dx - x0, y = cj * D->p.dy - y0;
@@ -873,9 +880,20 @@ int or_apply_edit(or_domain *D, int kind, double x0, double y0, double amp, doub
         if (!or_diag_dominant(D)) {
             memcpy(D->z, save, nz * sizeof(double));
             free(save);
+            free(hold);
             return -4;
         }
+        for (int j = 0; j < D->p.ny; ++j)
+            for (int i = 0; i < D->p.nx; ++i) {
+                double ho = hold[(size_t)j * D->p.nx + i], hn = D->w[CI(D, i, j)] - bcell(D, i, j);
+                if (hn < 0.0) hn = 0.0;
+                double f = ho > 0.0 ? hn / ho : 1.0;
+                if (f > 1.0) f = 1.0;
+                D->P[CI(D, i, j)] *= f;
+                D->Q[CI(D, i, j)] *= f;
+            }
         free(save);
+        free(hold);
     }
     dry_fix_w(D, D->w);
     dry_fix_pq(D, D->w, D->P, D->Q);

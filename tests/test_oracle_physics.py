@@ -370,3 +370,29 @@ def test_edits_keep_surface_above_bottom_and_reject_steep_terrain():
     z0 = L.bathy()[0].copy()
     assert L.apply_edit(o.EDIT_TERRAIN, 2.0, 1.5, -6.0, 0.06) == -4
     assert np.array_equal(L.bathy()[0], z0) and L.diag_dominant()
+
+
+def test_terrain_edit_keeps_surface_and_velocity():
+    """Raising the bed under a uniform current keeps the free surface and the
+    depth-averaged velocity wherever the cell stays wet (P, Q scale with the
+    remaining depth); cells the bump lifts out of the water hold no
+    momentum; lowering the bed never raises the momentum."""
+    nx, ny, dx, h0, u0, v0 = 40, 30, 0.1, 0.3, 0.4, -0.25
+    D = o.Domain(nx, ny, dx, dx, 0.01, -h0 * np.ones((ny + 1, nx + 1)))
+    D.set_state(np.zeros((ny, nx)), h0 * u0 * np.ones((ny, nx)), h0 * v0 * np.ones((ny, nx)))
+    assert D.apply_edit(o.EDIT_TERRAIN, 2.0, 1.5, 0.5, 0.5) == 0
+    w, P, Q = D.state()
+    b, _ = D.bathy()
+    h = w - b
+    wet = h > 1e-3
+    dry = h == 0
+    assert wet.sum() > 600 and dry.sum() > 4
+    assert np.array_equal(w[wet], np.zeros(wet.sum()))
+    np.testing.assert_allclose(P[wet] / h[wet], u0, rtol=1e-12)
+    np.testing.assert_allclose(Q[wet] / h[wet], v0, rtol=1e-12)
+    assert np.all(P[dry] == 0) and np.all(Q[dry] == 0)
+    L = o.Domain(nx, ny, dx, dx, 0.01, -h0 * np.ones((ny + 1, nx + 1)))
+    L.set_state(np.zeros((ny, nx)), h0 * u0 * np.ones((ny, nx)), np.zeros((ny, nx)))
+    assert L.apply_edit(o.EDIT_TERRAIN, 2.0, 1.5, -0.2, 0.5) == 0
+    _, P2, _ = L.state()
+    assert np.array_equal(P2, h0 * u0 * np.ones((ny, nx)))
