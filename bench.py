@@ -54,6 +54,9 @@ def parse():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-vs-plain ensemble measurement")
     ap.add_argument("--ens-steps", type=int, default=30, help="timed steps of the ensemble runs")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="wall seconds of the session-serving run (0: skip)")
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--no-k-variants", action="store_true",
                     help="skip the K = 0 and K = 1 corrector-count rates")
     return ap.parse_args()
@@ -136,6 +139,19 @@ def batched_vs_plain(args, torch, ws, wl):
             "batched_over_plain_graph": (cells * n / t_b) / (cells * 3 * reps / t_g),
             "batched_over_plain_eager": (cells * n / t_b) / (cells * n / t_p),
             "unit": "cell-updates/s", "healthy": all(h == 0 for h in health)}
+
+
+def serving(args):
+    """Session serving: the Poisson trace (4 sessions/s, grids 512^2..2048^2,
+    an edit every 50 steps) served with continuous batching for a bounded
+    wall-time window."""
+    from paper_1611_05984_amd import serving as sv
+    from paper_1611_05984_amd import workloads as wl
+    srv = sv.Server(budget_bytes=int(args.serve_budget_gb * 2**30), max_sessions=256, tick_steps=10)
+    rep = srv.run(wl.config5_trace(), wall_limit=args.serve_seconds,
+                  log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
+    rep["workload"] = "sessions_poisson4ps_512-2048_edits50"
+    return rep
 
 
 def k_variants(args, torch, ws, wl):
@@ -266,6 +282,9 @@ def main():
     if not args.no_batched:
         print("bench: ensemble batched vs plain", file=sys.stderr, flush=True)
         out["ensemble"] = batched_vs_plain(args, torch, ws, wl)
+    if args.serve_seconds > 0:
+        print("bench: session serving, %.0f s" % args.serve_seconds, file=sys.stderr, flush=True)
+        out["serving"] = serving(args)
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)

@@ -152,13 +152,28 @@ ws_status ws_read(ws_domain *d, int32_t what, float *first, float *P, float *Q, 
 
 /* Interactive edit (sec. 1): add a Gaussian hump amp*exp(-r^2/(2 sigma^2))
  * centred at (x0, y0) to the water surface (WS_EDIT_ADD_WATER) or to the
- * terrain corners (WS_EDIT_RAISE_TERRAIN; amp < 0 lowers it).  The surface
- * is then kept at or above the bottom and P, Q are desingularized where the
- * water is thinner than eps^(1/4).  A terrain edit that would make a system
+ * terrain corners (WS_EDIT_RAISE_TERRAIN; amp < 0 lowers it).  A terrain
+ * edit keeps the free surface and scales P, Q by the cell's remaining depth
+ * over its old depth (at most 1: the depth-averaged velocity is kept where
+ * the cell stays wet).  The surface is then kept at or above the bottom and
+ * P, Q are desingularized where the water is thinner than eps^(1/4).  A terrain edit that would make a system
  * of eq. 23 lose diagonal dominance is rejected with WS_ENOTDD and changes
  * nothing.  Synchronous for terrain edits, asynchronous for water edits. */
 ws_status ws_apply_edit(ws_domain *d, int32_t kind, double x0, double y0, double amp,
                         double sigma, void *stream);
+
+/* Snapshot / restore (checkpoint, session migration).  A snapshot holds the
+ * current state, the multistep history, the (possibly edited) bathymetry,
+ * the step count and the time, in a caller-owned device buffer of
+ * ws_snapshot_bytes(d) bytes (256-byte aligned).  Boundary settings are not
+ * part of it.  ws_snapshot is asynchronous on `stream`; ws_restore reads the
+ * header synchronously, returns WS_EINVAL if the snapshot was taken from a
+ * domain of another grid size, corrector count or model, then copies
+ * asynchronously.  Stepping on after a restore continues the run exactly as
+ * it would have continued from the snapshot. */
+size_t ws_snapshot_bytes(const ws_domain *d);
+ws_status ws_snapshot(ws_domain *d, void *dst_dev, size_t bytes, void *stream);
+ws_status ws_restore(ws_domain *d, const void *src_dev, size_t bytes, void *stream);
 
 /* Synchronize `stream` and report the number of completed steps, the
  * simulated time and the health word (0 = finite state).  Returns
@@ -192,14 +207,26 @@ size_t ws_batch_workspace_bytes(int32_t max_domains);
 ws_status ws_batch_create(int32_t max_domains, void *workspace_dev, size_t workspace_bytes,
                           ws_batch **out);
 ws_status ws_batch_destroy(ws_batch *b);
-/* Attach a domain (WS_EBUSY if the batch is full or the domain attached elsewhere). */
+/* Attach a domain (WS_EBUSY if the batch is full or the domain attached
+ * elsewhere).  No device call: may run while the batch's steps are in
+ * flight; the domain joins at the next ws_batch_advance. */
 ws_status ws_batch_attach(ws_batch *b, ws_domain *d, int32_t *slot);
 ws_status ws_batch_detach(ws_batch *b, int32_t slot);
-/* Advance every attached domain by nsteps full steps.  Asynchronous. */
+/* Step limit of one attached domain: the batch does not advance it past
+ * step `stop_step` (completed steps, as ws_query reports; -1 = no limit), so
+ * sessions pause at their next edit while the rest of the batch runs on.
+ * Takes effect at the next ws_batch_advance; no device call. */
+ws_status ws_batch_set_stop(ws_batch *b, int32_t slot, int64_t stop_step);
+/* Advance every attached domain by nsteps full steps (fewer for a domain
+ * that reaches its step limit).  Asynchronous. */
 ws_status ws_batch_advance(ws_batch *b, int64_t nsteps, void *stream);
 /* Synchronize `stream` and bring the attached domains' step, time and state
  * buffer index up to date on the host. */
 ws_status ws_batch_sync(ws_batch *b, void *stream);
+/* Step, simulated time and health word (0 = finite) of the domain in `slot`
+ * as of the last ws_batch_sync; host only, no device call.  WS_EBUSY if the
+ * batch has advanced since. */
+ws_status ws_batch_status(ws_batch *b, int32_t slot, int64_t *step, double *t, int32_t *health);
 
 /* Thread-local description of the last error. */
 const char *ws_last_error(void);

@@ -64,6 +64,8 @@ struct ws_domain {
     ws_batch *batch;               // batch this domain is attached to, if any
     int bidx;                      // its index in the batch's device tables
     bool stale;                    // the batch has advanced it since the last ws_batch_sync
+    int64_t stop;                  // batch step limit (-1: none)
+    int bhealth;                   // health word as of the last batch sync
     bool vdirty;                   // pass argument tables must be rewritten
     StencilArgs *vsa;              // pass argument tables (device), batch use only
     SolveArgs *vso;
@@ -262,6 +264,20 @@ __global__ void k_edit_terrain(Dom d, const float *Dold, float *Dnew, double x0,
     Dnew[o] = (float)((double)Dold[o] - amp * exp(-(x * x + y * y) / (2.0 * sigma * sigma)));
 }
 
+// After a terrain change (d holds the new depth, Dold the old one): the
+// surface is kept and the momentum scaled by remaining / old depth (at most
+// 1), which keeps the depth-averaged velocity of cells that stay wet.
+__global__ void k_edit_velocity(Dom d, const float *Dold, const float *e, float *p, float *q) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i >= d.nx || j >= d.ny) return;
+    Dom od = d;
+    od.D = Dold;
+    const size_t o = (size_t)j * d.pitch + i;
+    const float ho = e[o] + cell_Dc(od, i, j), hn = fmaxf(e[o] + cell_Dc(d, i, j), 0.f);
+    const float f = ho > 0.f ? fminf(hn / ho, 1.f) : 1.f;
+    p[o] *= f;
+    q[o] *= f;
+}
 __global__ void k_shore_fix(Dom d, float *e, float *p, float *q) {
     int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
     if (i >= d.nx || j >= d.ny) return;
@@ -479,6 +495,82 @@ extern "C" ws_status ws_set_boundary(ws_domain *d, int32_t side, const ws_bounda
     return WS_OK;
 }
 
+// ------------------------------------------------------- snapshot / restore
+// Snapshot layout: a 256-byte header, then the current state (eta, P, Q), the
+// three history slots (E, F, G, F*, G* each) and the corner depth, each as
+// the domain stores it (padded rows).
+struct SnapHeader {
+    unsigned long long magic;
+    int nx, ny, pitch, zpitch;
+    long long step;
+    double t;
+    int n_corr, model;
+    unsigned long long field_bytes, corner_bytes, total;
+};
+static const unsigned long long SNAP_MAGIC = 0x3130504e53535757ull;  // "WWSSNP01"
+
+static size_t snap_field_bytes(const ws_domain *d) { return sizeof(float) * (size_t)d->nyp * d->pitch; }
+static size_t snap_corner_bytes(const ws_domain *d) { return sizeof(float) * (size_t)(d->g.ny + 1) * d->zpitch; }
+
+extern "C" size_t ws_snapshot_bytes(const ws_domain *d) {
+    if (!d) return 0;
+    return 256 + 18 * snap_field_bytes(d) + snap_corner_bytes(d);
+}
+
+__global__ void k_snap_header(SnapHeader h, SnapHeader *dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = h;
+}
+
+extern "C" ws_status ws_snapshot(ws_domain *d, void *dst_dev, size_t bytes, void *stream) {
+    if (!d || !dst_dev) return fail(WS_EINVAL, "ws_snapshot: bad argument");
+    if (busy_check(d, "ws_snapshot") != WS_OK) return WS_EBUSY;
+    if (((uintptr_t)dst_dev & 255) != 0) return fail(WS_EINVAL, "ws_snapshot: buffer not 256-byte aligned");
+    const size_t need = ws_snapshot_bytes(d), fb = snap_field_bytes(d), cb = snap_corner_bytes(d);
+    if (bytes < need) return fail(WS_ENOMEM, "ws_snapshot: buffer %zu < %zu bytes", bytes, need);
+    hipStream_t st = (hipStream_t)stream;
+    SnapHeader h;
+    std::memset(&h, 0, sizeof h);
+    h.magic = SNAP_MAGIC;
+    h.nx = d->g.nx; h.ny = d->g.ny; h.pitch = d->pitch; h.zpitch = d->zpitch;
+    h.step = d->step; h.t = d->t;
+    h.n_corr = d->g.n_corr; h.model = d->g.model;
+    h.field_bytes = fb; h.corner_bytes = cb; h.total = need;
+    char *p = (char *)dst_dev;
+    hipLaunchKernelGGL(k_snap_header, dim3(1), dim3(64), 0, st, h, (SnapHeader *)p);
+    p += 256;
+    for (int f = 0; f < 3; ++f, p += fb) HIPCHK(hipMemcpyAsync(p, d->st[d->cur][f], fb, hipMemcpyDeviceToDevice, st));
+    for (int sl = 0; sl < 3; ++sl)
+        for (int f = 0; f < 5; ++f, p += fb) HIPCHK(hipMemcpyAsync(p, d->hist[sl][f], fb, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(p, d->D, cb, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipGetLastError());
+    return WS_OK;
+}
+
+extern "C" ws_status ws_restore(ws_domain *d, const void *src_dev, size_t bytes, void *stream) {
+    if (!d || !src_dev) return fail(WS_EINVAL, "ws_restore: bad argument");
+    if (busy_check(d, "ws_restore") != WS_OK) return WS_EBUSY;
+    const size_t need = ws_snapshot_bytes(d), fb = snap_field_bytes(d), cb = snap_corner_bytes(d);
+    if (bytes < need) return fail(WS_EINVAL, "ws_restore: buffer %zu < %zu bytes", bytes, need);
+    hipStream_t st = (hipStream_t)stream;
+    SnapHeader h;
+    HIPCHK(hipMemcpyAsync(&h, src_dev, sizeof h, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (h.magic != SNAP_MAGIC || h.nx != d->g.nx || h.ny != d->g.ny || h.pitch != d->pitch ||
+        h.zpitch != d->zpitch || h.total != need || h.n_corr != d->g.n_corr || h.model != d->g.model)
+        return fail(WS_EINVAL, "ws_restore: snapshot does not match this domain's grid");
+    const char *p = (const char *)src_dev + 256;
+    for (int f = 0; f < 3; ++f, p += fb) HIPCHK(hipMemcpyAsync(d->st[0][f], p, fb, hipMemcpyDeviceToDevice, st));
+    for (int sl = 0; sl < 3; ++sl)
+        for (int f = 0; f < 5; ++f, p += fb) HIPCHK(hipMemcpyAsync(d->hist[sl][f], p, fb, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(d->D, p, cb, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemsetAsync(d->health, 0, sizeof(int), st));
+    d->cur = 0;
+    d->step = h.step;
+    d->t = h.t;
+    batch_touch(d);
+    return WS_OK;
+}
+
 extern "C" ws_status ws_set_state(ws_domain *d, const float *w, const float *P, const float *Q,
                                   int32_t pitch, double t, void *stream) {
     if (!d || !w || !P || !Q || pitch < d->g.nx) return fail(WS_EINVAL, "ws_set_state: bad argument");
@@ -560,6 +652,7 @@ extern "C" ws_status ws_apply_edit(ws_domain *d, int32_t kind, double x0, double
     std::swap(d->D, d->Dnew);
     batch_touch(d);
     m = make_dom(d);
+    hipLaunchKernelGGL(k_edit_velocity, cells_grid(d->g.nx, d->g.ny), dim3(256), 0, st, m, d->Dnew, e, p, q);
     hipLaunchKernelGGL(k_shore_fix, cells_grid(d->g.nx, d->g.ny), dim3(256), 0, st, m, e, p, q);
     HIPCHK(hipGetLastError());
     return WS_OK;
@@ -751,6 +844,7 @@ static BatchDesc make_desc(const ws_domain *d) {
     D.nsys = d->g.ny + d->g.nx;
     D.makers = 0;
     for (int q = 0; q < 4; ++q) D.makers += d->side_type[q] == WS_BC_WAVES;
+    D.health = d->health;
     return D;
 }
 
@@ -784,6 +878,7 @@ static ws_status batch_pull(ws_batch *b, hipStream_t st) {
         d->step = b->h_state[k].step;
         d->t = b->h_state[k].t;
         d->cur = b->h_state[k].cur;
+        d->bhealth = b->h_state[k].health;
         d->stale = false;
     }
     b->stale = false;
@@ -815,7 +910,8 @@ static ws_status batch_upload(ws_batch *b) {
         b->h_state[k].step = d->step;
         b->h_state[k].t = d->t;
         b->h_state[k].cur = d->cur;
-        b->h_state[k].pad = 0;
+        b->h_state[k].stop = d->stop;
+        b->h_state[k].health = 0;
         const BatchDesc &D = desc[k];
         pre[0][k + 1] = pre[0][k] + D.sgx * D.sgy;
         pre[1][k + 1] = pre[1][k] + D.tgx * D.tgy;
@@ -902,12 +998,13 @@ extern "C" ws_status ws_batch_destroy(ws_batch *b) {
 extern "C" ws_status ws_batch_attach(ws_batch *b, ws_domain *d, int32_t *slot) {
     if (!b || !d) return fail(WS_EINVAL, "ws_batch_attach: bad argument");
     if (d->batch) return fail(WS_EBUSY, "ws_batch_attach: domain already attached");
-    if (batch_pull(b, b->last) != WS_OK) return WS_EHIP;
+    // no sync: the tables are rebuilt (after a pull) by the next ws_batch_advance
     for (int sl = 0; sl < b->max; ++sl)
         if (!b->slots[sl]) {
             b->slots[sl] = d;
             d->batch = b;
             d->stale = false;
+            d->stop = -1;
             b->dirty = true;
             if (slot) *slot = sl;
             return WS_OK;
@@ -923,6 +1020,24 @@ extern "C" ws_status ws_batch_detach(ws_batch *b, int32_t slot) {
     d->stale = false;
     b->slots[slot] = nullptr;
     b->dirty = true;
+    return WS_OK;
+}
+
+extern "C" ws_status ws_batch_set_stop(ws_batch *b, int32_t slot, int64_t stop_step) {
+    if (!b || slot < 0 || slot >= b->max || !b->slots[slot]) return fail(WS_EINVAL, "ws_batch_set_stop: bad slot");
+    ws_domain *d = b->slots[slot];
+    d->stop = stop_step < 0 ? -1 : stop_step;  // uploaded (after a pull) by the next ws_batch_advance
+    b->dirty = true;
+    return WS_OK;
+}
+
+extern "C" ws_status ws_batch_status(ws_batch *b, int32_t slot, int64_t *step, double *t, int32_t *health) {
+    if (!b || slot < 0 || slot >= b->max || !b->slots[slot]) return fail(WS_EINVAL, "ws_batch_status: bad slot");
+    if (b->stale) return fail(WS_EBUSY, "ws_batch_status: call ws_batch_sync first");
+    const ws_domain *d = b->slots[slot];
+    if (step) *step = d->step;
+    if (t) *t = d->t;
+    if (health) *health = d->bhealth;
     return WS_OK;
 }
 

@@ -32,20 +32,26 @@ struct BatchDesc {
     int nsys;                  // reduced systems: ny + nx
     int makers;                // number of wave-maker sides
     int pad;
+    const int *health;         // the domain's health word
 };
 
 struct BatchState {
     long long step;            // completed steps since (re)start
+    long long stop;            // pause once step reaches it (-1: no limit)
     double t;
     int cur;                   // state buffer of the current state
-    int pad;
+    int health;                // copy of the domain's health word after the step
 };
 
+__device__ __forceinline__ bool paused(const BatchState &S) { return S.stop >= 0 && S.step >= S.stop; }
+
 // Argument-table entry of pass p of the step a domain takes next, or -1 when
-// the domain has no such pass (correctors of the Euler start-up steps).
+// the domain has no such pass (correctors of the Euler start-up steps) or is
+// paused at its step limit.
 // Entries 0..8: Euler steps by (state buffer, step mod 3); then full steps by
 // (state buffer, step mod 3, pass).
 __device__ __forceinline__ int variant(const BatchDesc &D, const BatchState &S, int p) {
+    if (paused(S)) return -1;
     const long long s = S.step + 1;
     const int sm = (int)(s % 3), key = S.cur * 3 + sm;
     if (s <= 2) return p == 0 ? key : -1;
@@ -139,7 +145,7 @@ __global__ void kb_ghosts(const BatchDesc *descs, const BatchState *states, cons
                           int which) {
     const int b = blockIdx.x, dm = find_dom(prefix, ndom, b);
     const BatchDesc &D = descs[dm];
-    if (!D.makers) return;
+    if (!D.makers || paused(states[dm])) return;
     const int k = (b - prefix[dm]) * blockDim.x + threadIdx.x;
     if (k >= 8 * D.d.gl) return;
     const double t = states[dm].t + (which ? D.dt : 0.0);
@@ -151,6 +157,11 @@ __global__ void kb_finish(const BatchDesc *descs, BatchState *states, int ndom) 
     const int dm = blockIdx.x * blockDim.x + threadIdx.x;
     if (dm >= ndom) return;
     BatchState S = states[dm];
+    S.health = *descs[dm].health;
+    if (paused(S)) {
+        states[dm] = S;
+        return;
+    }
     const long long s = S.step + 1;
     const int K = s <= 2 ? 0 : descs[dm].K;
     const int b = (S.cur + 1) % 3, c = (S.cur + 2) % 3;

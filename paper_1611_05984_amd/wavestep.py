@@ -75,12 +75,17 @@ def lib():
             "ws_last_error": (C.c_char_p, []),
             "ws_profile_enable": (C.c_int, [vp, i32]),
             "ws_profile_collect": (C.c_int, [vp, vp, C.POINTER(f64), C.POINTER(i64), i32]),
+            "ws_snapshot_bytes": (sz, [vp]),
+            "ws_snapshot": (C.c_int, [vp, vp, sz, vp]),
+            "ws_restore": (C.c_int, [vp, vp, sz, vp]),
             "ws_batch_workspace_bytes": (sz, [i32]),
             "ws_batch_create": (C.c_int, [i32, vp, sz, C.POINTER(vp)]),
             "ws_batch_destroy": (C.c_int, [vp]),
             "ws_batch_attach": (C.c_int, [vp, vp, C.POINTER(i32)]),
             "ws_batch_detach": (C.c_int, [vp, i32]),
             "ws_batch_advance": (C.c_int, [vp, i64, vp]),
+            "ws_batch_set_stop": (C.c_int, [vp, i32, i64]),
+            "ws_batch_status": (C.c_int, [vp, i32, C.POINTER(i64), C.POINTER(f64), C.POINTER(i32)]),
             "ws_batch_sync": (C.c_int, [vp, vp]),
         }
         for name, (res, args) in sigs.items():
@@ -209,6 +214,17 @@ class Domain:
             _check(st, "ws_query")
         return step.value, t.value, health.value
 
+    def snapshot(self, stream=None):
+        """Device snapshot (uint8 tensor) of state, history, bathymetry, step and time."""
+        import torch
+        n = int(lib().ws_snapshot_bytes(self._h))
+        buf = torch.empty(n, dtype=torch.uint8, device=self.device)
+        _check(lib().ws_snapshot(self._h, _dptr(buf), n, _stream(stream)), "ws_snapshot")
+        return buf
+
+    def restore(self, buf, stream=None):
+        _check(lib().ws_restore(self._h, _dptr(buf), buf.numel(), _stream(stream)), "ws_restore")
+
     def profile(self, on=True):
         _check(lib().ws_profile_enable(self._h, 1 if on else 0), "ws_profile_enable")
 
@@ -255,6 +271,10 @@ class Batch:
         _check(lib().ws_batch_detach(self._h, int(slot)), "ws_batch_detach")
         return self.domains.pop(int(slot))
 
+    def set_stop(self, slot, stop_step):
+        """Do not advance the domain in `slot` past step `stop_step` (-1: no limit)."""
+        _check(lib().ws_batch_set_stop(self._h, int(slot), int(stop_step)), "ws_batch_set_stop")
+
     def advance(self, n):
         import torch
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
@@ -263,6 +283,13 @@ class Batch:
 
     def sync(self):
         _check(lib().ws_batch_sync(self._h, C.c_void_p(self.stream.cuda_stream)), "ws_batch_sync")
+
+    def status(self, slot):
+        """(step, t, health) of the domain in `slot` as of the last sync."""
+        step, t, health = C.c_int64(), C.c_double(), C.c_int32()
+        _check(lib().ws_batch_status(self._h, int(slot), C.byref(step), C.byref(t), C.byref(health)),
+               "ws_batch_status")
+        return step.value, t.value, health.value
 
     def close(self):
         if getattr(self, "_h", None):

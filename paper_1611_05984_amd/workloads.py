@@ -211,16 +211,21 @@ class Session:
     slope: float
     steps: int
     edits: list   # (step, kind, x0, y0, amp, sigma)
+    courant: float = 0.2
+    eps: float = 5e-12    # desingularization threshold of the session's solver
 
 
 def config5_trace(rate: float = 4.0, duration: float = 600.0, seed: int = 5,
-                  sizes=(512, 1024, 2048), edit_every: int = 50) -> list:
+                  sizes=(512, 1024, 2048), edit_every: int = 50, steps=(500, 2000),
+                  sigma_cells=(10.0, 40.0), water_amp=(0.1, 0.5), terrain_amp=(0.2, 1.0),
+                  eps: float = 5e-12) -> list:
     """Poisson arrivals (rate per second) over `duration` seconds.  Per
     session, in draw order: inter-arrival gap, grid size (uniform over
     `sizes`), offshore depth U[0.5, 2] m, beach slope U[1/50, 1/10], session
-    length U{500..2000} steps, then for each edit (every `edit_every` steps):
+    length U{steps[0]..steps[1]} (default 500..2000) steps, then for each edit (every `edit_every` steps):
     kind (0 water hump A ~ U[0.1, 0.5] m, 1 terrain A ~ U[0.2, 1] m, p = 1/2),
-    sigma ~ U[10, 40] cells, centre uniform, amplitude."""
+    sigma ~ U[10, 40] cells, centre uniform, amplitude (ranges adjustable for
+    small test traces)."""
     rng = np.random.default_rng(seed)
     t, out = 0.0, []
     dx = 0.1
@@ -231,20 +236,20 @@ def config5_trace(rate: float = 4.0, duration: float = 600.0, seed: int = 5,
         n = int(sizes[int(rng.integers(0, len(sizes)))])
         depth = float(rng.uniform(0.5, 2.0))
         slope = float(rng.uniform(1 / 50, 1 / 10))
-        steps = int(rng.integers(500, 2001))
+        n_steps = int(rng.integers(steps[0], steps[1] + 1))
         edits = []
-        for s in range(edit_every, steps + 1, edit_every):
+        for s in range(edit_every, n_steps + 1, edit_every):
             kind = int(rng.integers(0, 2))
-            sigma = float(rng.uniform(10, 40)) * dx
+            sigma = float(rng.uniform(*sigma_cells)) * dx
             x0, y0 = float(rng.uniform(0, n * dx)), float(rng.uniform(0, n * dx))
-            amp = float(rng.uniform(0.1, 0.5)) if kind == 0 else float(rng.uniform(0.2, 1.0))
+            amp = float(rng.uniform(*water_amp)) if kind == 0 else float(rng.uniform(*terrain_amp))
             edits.append((s, kind, x0, y0, amp, sigma))
-        out.append(Session(t, n, depth, slope, steps, edits))
+        out.append(Session(t, n, depth, slope, n_steps, edits, eps=eps))
     return out
 
 
 def session_workload(s: Session) -> Workload:
     dx = 0.1
     z = beach_or_flat(s.nx, s.nx, dx, s.depth, s.slope)
-    return Workload("session_%d" % s.nx, s.nx, s.nx, dx, dx, courant_dt(0.2, dx, s.depth), z,
+    return Workload("session_%d" % s.nx, s.nx, s.nx, dx, dx, courant_dt(s.courant, dx, s.depth), z,
                     walls(), steps=s.steps)

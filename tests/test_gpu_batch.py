@@ -190,3 +190,31 @@ def test_config4_full_size_batch_sampled_vs_alone():
     bad = [k for k, d in enumerate(doms) if d.query()[2] != 0]
     assert not bad, bad
     B.close()
+
+
+def test_snapshot_restore_continues_exactly():
+    """A snapshot (state, history, edited bathymetry, step, time) restored
+    into a fresh domain of the same grid continues bit for bit as the
+    original run; a snapshot of another grid is refused."""
+    ws = _ws()
+    w = wl.config2(nx=160, ny=72, seed=9)
+    say("case: snapshot / restore on %s" % w.name)
+    a = make(w)
+    a.advance(25)
+    assert a.apply_edit(ws.EDIT_TERRAIN, 0.6 * w.nx * w.dx, 0.5 * w.ny * w.dy, 0.2, 5 * w.dx) == 0
+    a.advance(5)
+    snap = a.snapshot()
+    a.advance(20)
+    b = make(w)                                    # same grid and boundaries, fresh state
+    b.advance(3)
+    b.restore(snap)
+    assert b.query()[0] == 30
+    b.advance(20)
+    same(a, b, "restored run")
+    a.restore(snap)                                # rewind the original in place
+    a.advance(20)
+    same(a, b, "rewound run")
+    other = make(wl.config1(nx=64, ny=32))
+    with pytest.raises(ws.WaveStepError) as e:
+        other.restore(snap)
+    assert e.value.status == ws.EINVAL

@@ -185,6 +185,31 @@ def test_edits_and_state_round_trip():
     assert np.abs(gh - (ge - b)).max() < 1e-5
 
 
+def test_terrain_edit_keeps_velocity_like_oracle():
+    """Bed raised through a uniform current: surface and depth-averaged
+    velocity kept where wet, no momentum where the bump emerges; element by
+    element against the oracle right after the edit and 20 steps later."""
+    say("case: terrain edit under a current 64x48")
+    ws = _ws()
+    nx, ny, dx, h0 = 64, 48, 0.1, 0.3
+    z = -h0 * np.ones((ny + 1, nx + 1))
+    gpu = ws.Domain(nx, ny, dx, dx, 0.004, z)
+    ora = o.Domain(nx, ny, dx, dx, 0.004, z)
+    w0 = np.zeros((ny, nx))
+    P0, Q0 = h0 * 0.4 * np.ones((ny, nx)), h0 * -0.25 * np.ones((ny, nx))
+    gpu.set_state(w0.astype(np.float32), P0.astype(np.float32), Q0.astype(np.float32))
+    ora.set_state(w0, P0, Q0)
+    assert gpu.apply_edit(ws.EDIT_TERRAIN, 3.2, 2.4, 0.5, 0.6) == 0
+    assert ora.apply_edit(ws.EDIT_TERRAIN, 3.2, 2.4, 0.5, 0.6) == 0
+    ge, gP, gQ = gpu.state_numpy()
+    oe, oP, oQ = ora.state()
+    assert np.abs(ge - oe).max() <= 1e-6 and np.abs(gP - oP).max() <= 1e-6 * 0.12
+    assert np.abs(gQ - oQ).max() <= 1e-6 * 0.12
+    gpu.advance(20)
+    ora.advance(20)
+    check(gpu, ora, 0.3, h0, rel=1e-4, what="20 steps after the edit")
+
+
 def test_steep_terrain_edit_rejected_unchanged():
     say("case: rejected terrain edit")
     ws = _ws()
