@@ -228,6 +228,34 @@ ws_status ws_batch_sync(ws_batch *b, void *stream);
  * batch has advanced since. */
 ws_status ws_batch_status(ws_batch *b, int32_t slot, int64_t *step, double *t, int32_t *health);
 
+/* ---- Tuning: launch shapes chosen per grid shape.
+ * stencil_rows: rows each stencil workgroup streams (8, 16, 24, 32, 48 or
+ * 64; taller strips repeat fewer warm-up rows, shorter ones give more
+ * workgroups and a smaller last wave of workgroups).  pcr_threads: threads
+ * per reduced tridiagonal system in the partitioned solve (64, 128 or 256:
+ * equations held per thread versus threads per barrier).  Results do not
+ * depend on the tuning (bitwise). */
+typedef struct {
+    int32_t stencil_rows;
+    int32_t pcr_threads;
+    int32_t reserved[6];
+} ws_tuning;
+ws_status ws_get_tuning(const ws_domain *d, ws_tuning *out);
+ws_status ws_set_tuning(ws_domain *d, const ws_tuning *t);
+/* Tuning of a batch (shared by its domains; default 32 rows, 128 threads). */
+ws_status ws_batch_set_tuning(ws_batch *b, const ws_tuning *t);
+/* Autotuner: times every candidate launch shape on this domain's grid
+ * (corrector-pass stencil and the reduced solves, HIP events on `stream`;
+ * the domain's state and history are not changed), applies the fastest and
+ * returns it in *out.  With a cache file (may be NULL), a shape already
+ * measured is read from it instead, and new results are appended to it as
+ * lines "nx ny n_corr model stencil_rows pcr_threads".  Synchronous. */
+ws_status ws_tune(ws_domain *d, const char *cache_path, void *stream, ws_tuning *out);
+/* Autotuner of a batch: the same candidates timed on the batched kernels over
+ * all attached domains (a corrector pass, writing only scratch), applied to
+ * the batch and returned.  Synchronous. */
+ws_status ws_batch_tune(ws_batch *b, void *stream, ws_tuning *out);
+
 /* Thread-local description of the last error. */
 const char *ws_last_error(void);
 

@@ -67,6 +67,8 @@ struct ws_domain {
     int64_t stop;                  // batch step limit (-1: none)
     int bhealth;                   // health word as of the last batch sync
     bool vdirty;                   // pass argument tables must be rewritten
+    int sy, pnt;                   // tuning: stencil rows per strip, PCR threads per system
+    size_t fstride;                // bytes between consecutive fields
     StencilArgs *vsa;              // pass argument tables (device), batch use only
     SolveArgs *vso;
     int nvar;
@@ -366,6 +368,9 @@ extern "C" ws_status ws_domain_init(const ws_grid *g, const float *z_corners_dev
     d->vsa = (StencilArgs *)take(L.vtab);
     d->vso = (SolveArgs *)(d->vsa + L.nvar);
     d->vdirty = true;
+    d->sy = SY;
+    d->pnt = PCR_NT;
+    d->fstride = L.field;
     for (int s = 0; s < 4; ++s) { d->side_type[s] = WS_BC_SOLID; d->side_width[s] = 2; }
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipMemsetAsync(d->base, 0, L.total, st);
@@ -658,9 +663,67 @@ extern "C" ws_status ws_apply_edit(ws_domain *d, int32_t kind, double x0, double
     return WS_OK;
 }
 
-static dim3 strips(const ws_domain *d) {
+static dim3 strips_for(const ws_domain *d, int sy) {
     const int ns = (d->g.nx + SO - 1) / SO;
-    return dim3((ns + SWG - 1) / SWG, (d->g.ny + SY - 1) / SY);
+    return dim3((ns + SWG - 1) / SWG, (d->g.ny + sy - 1) / sy);
+}
+static dim3 strips(const ws_domain *d) { return strips_for(d, d->sy); }
+
+#define SY_SWITCH(K, sy, LAUNCH)                        \
+    do {                                                \
+        if (sy == 8) LAUNCH(K<8>);                      \
+        else if (sy == 16) LAUNCH(K<16>);               \
+        else if (sy == 24) LAUNCH(K<24>);               \
+        else if (sy == 48) LAUNCH(K<48>);               \
+        else if (sy == 64) LAUNCH(K<64>);               \
+        else LAUNCH(K<32>);                             \
+    } while (0)
+
+static void launch_stencil(int sy, dim3 grid, hipStream_t st, const StencilArgs &sa) {
+#define L3(KERN) hipLaunchKernelGGL(KERN, grid, dim3(64 * SWG), 0, st, sa)
+    SY_SWITCH(k_stencil, sy, L3);
+#undef L3
+}
+// Equations per thread for systems of up to nred unknowns: a power of two.
+static int pcr_epl(int pnt, int nred) {
+    int e = 1;
+    while (e * pnt < nred) e *= 2;
+    return e;
+}
+
+// Launches by (threads per system, equations per thread); `Go` is called
+// with the kernel's template arguments as a tag.
+template <int PNT, int EPL> struct PcrShape {
+    static constexpr int threads = PNT, epl = EPL;
+};
+template <class Go> static void pcr_dispatch(int pnt, int epl, Go go) {
+    if (pnt == 64) {
+        if (epl <= 1) go(PcrShape<64, 1>());
+        else if (epl <= 2) go(PcrShape<64, 2>());
+        else if (epl <= 4) go(PcrShape<64, 4>());
+        else if (epl <= 8) go(PcrShape<64, 8>());
+        else if (epl <= 16) go(PcrShape<64, 16>());
+        else go(PcrShape<64, 32>());
+    } else if (pnt == 256) {
+        if (epl <= 1) go(PcrShape<256, 1>());
+        else if (epl <= 2) go(PcrShape<256, 2>());
+        else if (epl <= 4) go(PcrShape<256, 4>());
+        else go(PcrShape<256, 8>());
+    } else {
+        if (epl <= 1) go(PcrShape<128, 1>());
+        else if (epl <= 2) go(PcrShape<128, 2>());
+        else if (epl <= 4) go(PcrShape<128, 4>());
+        else if (epl <= 8) go(PcrShape<128, 8>());
+        else go(PcrShape<128, 16>());
+    }
+}
+
+static void launch_pcr(int pnt, int nred, int nsys, hipStream_t st, const SolveArgs &so) {
+    const size_t shm = sizeof(float4) * nred;
+    pcr_dispatch(pnt, pcr_epl(pnt, nred), [&](auto shape) {
+        using S = decltype(shape);
+        hipLaunchKernelGGL((k_pcr<S::threads, S::epl>), dim3(nsys), dim3(S::threads), shm, st, so);
+    });
 }
 
 // One predictor or corrector pass: stencil, then the partitioned solves.
@@ -677,16 +740,14 @@ static void pass_args(const ws_domain *d, const Dom &m, bool euler, int cur, int
     std::memset(&sa, 0, sizeof sa);
     sa.d = m;
     sa.d.gh = d->ghost[p == 0 ? 0 : 1];
-    sa.ein = d->st[in][0]; sa.pin = d->st[in][1]; sa.qin = d->st[in][2];
+    sa.in = d->st[in][0];
     sa.eout = d->st[out][0];
-    sa.rx = d->rx; sa.ry = d->ry;
-    sa.hE = d->hist[n0][0]; sa.hF = d->hist[n0][1]; sa.hG = d->hist[n0][2];
-    sa.hFs = d->hist[n0][3]; sa.hGs = d->hist[n0][4];
-    sa.E1 = d->hist[n1][0]; sa.F1 = d->hist[n1][1]; sa.G1 = d->hist[n1][2];
-    sa.Fs1 = d->hist[n1][3]; sa.Gs1 = d->hist[n1][4];
-    sa.E2 = d->hist[n2][0]; sa.F2 = d->hist[n2][1]; sa.G2 = d->hist[n2][2];
-    sa.Fs2 = d->hist[n2][3]; sa.Gs2 = d->hist[n2][4];
-    sa.Se = d->S[0]; sa.SU = d->S[1]; sa.SV = d->S[2];
+    sa.rxy = d->rx;
+    sa.h0 = d->hist[n0][0];
+    sa.h1 = d->hist[n1][0];
+    sa.h2 = d->hist[n2][0];
+    sa.S = d->S[0];
+    sa.fstride = (unsigned)d->fstride;
     sa.dt = (float)g.dt;
     sa.x0 = sa.x1 = sa.x2 = 0.f;
     if (g.fstar_extrap == 2) { sa.x0 = 2.f; sa.x1 = -3.f; sa.x2 = 1.f; }
@@ -721,7 +782,7 @@ static bool has_makers(const ws_domain *d) {
 static ws_status run_pass(ws_domain *d, const StencilArgs &sa, const SolveArgs &so, hipStream_t st) {
     {
         ProfScope p(d, st, sa.kind == 2 ? WS_K_CORRECTOR : WS_K_PREDICTOR);
-        hipLaunchKernelGGL(k_stencil, strips(d), dim3(64 * SWG), 0, st, sa);
+        launch_stencil(d->sy, strips(d), st, sa);
     }
     {
         ProfScope p(d, st, WS_K_REDUCE);
@@ -730,7 +791,7 @@ static ws_status run_pass(ws_domain *d, const StencilArgs &sa, const SolveArgs &
     {
         ProfScope p(d, st, WS_K_PCR);
         const int nred = d->nu > d->nv ? d->nu : d->nv;
-        hipLaunchKernelGGL(k_pcr, dim3(d->g.ny + d->g.nx), dim3(PCR_NT), sizeof(float4) * nred, st, so);
+        launch_pcr(d->pnt, nred, d->g.ny + d->g.nx, st, so);
     }
     {
         ProfScope p(d, st, WS_K_EXPAND);
@@ -801,6 +862,7 @@ struct ws_batch {
     hipGraphExec_t exec = nullptr;
     hipStream_t gstream = nullptr;
     hipStream_t last = nullptr;
+    int sy = SY, pnt = PCR_NT;           // tuning shared by all domains of the batch
 };
 
 static size_t batch_layout(int max, size_t *o_state, size_t *o_pre) {
@@ -826,7 +888,7 @@ static void batch_drop_graph(ws_batch *b) {
     b->gstream = nullptr;
 }
 
-static BatchDesc make_desc(const ws_domain *d) {
+static BatchDesc make_desc(const ws_domain *d, int sy) {
     BatchDesc D;
     std::memset(&D, 0, sizeof D);
     D.d = make_dom(d);
@@ -836,7 +898,7 @@ static BatchDesc make_desc(const ws_domain *d) {
     D.ghost[1] = d->ghost[1];
     D.dt = d->g.dt;
     D.K = d->g.n_corr;
-    const dim3 sg = strips(d);
+    const dim3 sg = strips_for(d, sy);
     D.sgx = (int)sg.x;
     D.sgy = (int)sg.y;
     D.tgx = d->nxp / TX;
@@ -906,7 +968,7 @@ static ws_status batch_upload(ws_batch *b) {
             if (r != WS_OK) return r;
         }
         d->bidx = k;
-        desc[k] = make_desc(d);
+        desc[k] = make_desc(d, b->sy);
         b->h_state[k].step = d->step;
         b->h_state[k].t = d->t;
         b->h_state[k].cur = d->cur;
@@ -946,10 +1008,17 @@ static ws_status batch_step(ws_batch *b, hipStream_t st) {
         hipLaunchKernelGGL(kb_ghosts, dim3(b->total[3]), dim3(256), 0, st, b->d_desc, b->d_state, b->d_pre[3], n, 1);
     }
     for (int p = 0; p <= b->maxK; ++p) {
-        hipLaunchKernelGGL(kb_stencil, dim3(b->total[0]), dim3(64 * SWG), 0, st, b->d_desc, b->d_state, b->d_pre[0], n, p);
+        const dim3 sg(b->total[0]), pg(b->total[2]);
+#define L4(KERN) hipLaunchKernelGGL(KERN, sg, dim3(64 * SWG), 0, st, b->d_desc, b->d_state, b->d_pre[0], n, p)
+        SY_SWITCH(kb_stencil, b->sy, L4);
+#undef L4
         hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NT), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, p);
-        hipLaunchKernelGGL(kb_pcr, dim3(b->total[2]), dim3(PCR_NT), sizeof(float4) * b->nred, st, b->d_desc,
-                           b->d_state, b->d_pre[2], n, p);
+        const size_t shm = sizeof(float4) * b->nred;
+        pcr_dispatch(b->pnt, pcr_epl(b->pnt, b->nred), [&](auto shape) {
+            using S = decltype(shape);
+            hipLaunchKernelGGL((kb_pcr<S::threads, S::epl>), pg, dim3(S::threads), shm, st, b->d_desc, b->d_state,
+                               b->d_pre[2], n, p);
+        });
         hipLaunchKernelGGL(kb_expand, dim3(b->total[1]), dim3(NT), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, p);
     }
     hipLaunchKernelGGL(kb_finish, dim3((n + 255) / 256), dim3(256), 0, st, b->d_desc, b->d_state, n);
@@ -1085,4 +1154,199 @@ extern "C" ws_status ws_batch_advance(ws_batch *b, int64_t nsteps, void *stream)
 extern "C" ws_status ws_batch_sync(ws_batch *b, void *stream) {
     if (!b) return fail(WS_EINVAL, "ws_batch_sync: NULL batch");
     return batch_pull(b, (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------------ tuning
+static bool tuning_ok(const ws_tuning *t) {
+    return t && (t->stencil_rows == 8 || t->stencil_rows == 16 || t->stencil_rows == 24 ||
+                 t->stencil_rows == 32 || t->stencil_rows == 48 || t->stencil_rows == 64) &&
+           (t->pcr_threads == 64 || t->pcr_threads == 128 || t->pcr_threads == 256);
+}
+
+extern "C" ws_status ws_get_tuning(const ws_domain *d, ws_tuning *out) {
+    if (!d || !out) return fail(WS_EINVAL, "ws_get_tuning: bad argument");
+    std::memset(out, 0, sizeof *out);
+    out->stencil_rows = d->sy;
+    out->pcr_threads = d->pnt;
+    return WS_OK;
+}
+
+extern "C" ws_status ws_set_tuning(ws_domain *d, const ws_tuning *t) {
+    if (!d || !tuning_ok(t)) return fail(WS_EINVAL, "ws_set_tuning: bad tuning");
+    d->sy = t->stencil_rows;
+    d->pnt = t->pcr_threads;
+    return WS_OK;
+}
+
+extern "C" ws_status ws_batch_set_tuning(ws_batch *b, const ws_tuning *t) {
+    if (!b || !tuning_ok(t)) return fail(WS_EINVAL, "ws_batch_set_tuning: bad tuning");
+    if (b->sy != t->stencil_rows || b->pnt != t->pcr_threads) {
+        b->sy = t->stencil_rows;
+        b->pnt = t->pcr_threads;
+        b->dirty = true;
+        b->total[0] = -1;  // launch shapes change: the captured step is rebuilt
+    }
+    return WS_OK;
+}
+
+static bool cache_lookup(const char *path, const ws_grid &g, ws_tuning *t) {
+    if (!path) return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    int nx, ny, k, m, sy, pn;
+    bool hit = false;
+    while (std::fscanf(f, "%d %d %d %d %d %d", &nx, &ny, &k, &m, &sy, &pn) == 6) {
+        if (nx == g.nx && ny == g.ny && k == g.n_corr && m == g.model) {
+            t->stencil_rows = sy;
+            t->pcr_threads = pn;
+            hit = tuning_ok(t);
+        }
+    }
+    std::fclose(f);
+    return hit;
+}
+
+extern "C" ws_status ws_tune(ws_domain *d, const char *cache_path, void *stream, ws_tuning *out) {
+    if (!d || !out) return fail(WS_EINVAL, "ws_tune: bad argument");
+    if (busy_check(d, "ws_tune") != WS_OK) return WS_EBUSY;
+    ws_tuning best;
+    std::memset(&best, 0, sizeof best);
+    if (cache_lookup(cache_path, d->g, &best)) {
+        ws_status r = ws_set_tuning(d, &best);
+        if (r == WS_OK) *out = best;
+        return r;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    // a corrector pass reads the current state and the corrector bases and
+    // writes only the scratch estimate, the U*, V* increments and the solver
+    // scratch: the state and history are untouched
+    const Dom m = make_dom(d);
+    StencilArgs sa;
+    SolveArgs so;
+    pass_args(d, m, false, d->cur, (int)((d->step + 1) % 3), d->g.n_corr > 0 ? 1 : 0, sa, so);
+    sa.kind = 2;
+    so.eta = d->st[(d->cur + 2) % 3][0];
+    so.pout = d->st[(d->cur + 2) % 3][1];
+    so.qout = d->st[(d->cur + 2) % 3][2];
+    sa.eout = so.eta;
+    so.sponge = 0;
+    so.health = (int *)d->scal;  // keep the domain's health word out of the timing runs
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const int reps = 5;
+    float best_s = 1e30f, best_p = 1e30f;
+    best.stencil_rows = SY;
+    best.pcr_threads = PCR_NT;
+    const int rows[6] = {8, 16, 24, 32, 48, 64};
+    for (int c = 0; c < 6; ++c) {
+        const dim3 grid = strips_for(d, rows[c]);
+        launch_stencil(rows[c], grid, st, sa);  // warm-up
+        HIPCHK(hipEventRecord(e0, st));
+        for (int k = 0; k < reps; ++k) launch_stencil(rows[c], grid, st, sa);
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_s) { best_s = ms; best.stencil_rows = rows[c]; }
+    }
+    // the reduced systems need valid equations: one reduction of the increments
+    hipLaunchKernelGGL(k_reduce, tiles(d), dim3(NT), 0, st, so);
+    const int nred = d->nu > d->nv ? d->nu : d->nv;
+    const int threads[3] = {64, 128, 256};
+    for (int c = 0; c < 3; ++c) {
+        launch_pcr(threads[c], nred, d->g.ny + d->g.nx, st, so);
+        HIPCHK(hipEventRecord(e0, st));
+        for (int k = 0; k < reps; ++k) launch_pcr(threads[c], nred, d->g.ny + d->g.nx, st, so);
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_p) { best_p = ms; best.pcr_threads = threads[c]; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(hipGetLastError());
+    if (cache_path) {
+        FILE *f = std::fopen(cache_path, "a");
+        if (f) {
+            std::fprintf(f, "%d %d %d %d %d %d\n", d->g.nx, d->g.ny, d->g.n_corr, d->g.model, best.stencil_rows,
+                         best.pcr_threads);
+            std::fclose(f);
+        }
+    }
+    ws_status r = ws_set_tuning(d, &best);
+    if (r == WS_OK) *out = best;
+    return r;
+}
+
+// Batch autotuner: times the batched stencil of a corrector pass (pass 1:
+// reads the states and corrector bases, writes only scratch) for every strip
+// height, then the batched reduced solves for every thread count, and keeps
+// the fastest.  Domains still in their start-up steps take no part.
+extern "C" ws_status ws_batch_tune(ws_batch *b, void *stream, ws_tuning *out) {
+    if (!b || !out) return fail(WS_EINVAL, "ws_batch_tune: bad argument");
+    hipStream_t st = (hipStream_t)stream;
+    ws_status r = batch_pull(b, b->last);
+    if (r != WS_OK) return r;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    auto time_it = [&](auto &&launch) -> float {
+        launch();
+        (void)hipEventRecord(e0, st);
+        for (int k = 0; k < 3; ++k) launch();
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        return ms;
+    };
+    const int rows[6] = {8, 16, 24, 32, 48, 64}, threads[3] = {64, 128, 256};
+    int best_sy = b->sy, best_pnt = b->pnt;
+    float best = 1e30f;
+    for (int c = 0; c < 6; ++c) {
+        b->sy = rows[c];
+        b->dirty = true;
+        if ((r = batch_upload(b)) != WS_OK) return r;
+        const int n = (int)b->order.size();
+        if (n == 0) break;
+        const float ms = time_it([&] {
+            const dim3 sg(b->total[0]);
+#define L5(KERN) hipLaunchKernelGGL(KERN, sg, dim3(64 * SWG), 0, st, b->d_desc, b->d_state, b->d_pre[0], n, 1)
+            SY_SWITCH(kb_stencil, b->sy, L5);
+#undef L5
+        });
+        if (ms < best) { best = ms; best_sy = rows[c]; }
+    }
+    b->sy = best_sy;
+    b->dirty = true;
+    if ((r = batch_upload(b)) != WS_OK) return r;
+    const int n = (int)b->order.size();
+    best = 1e30f;
+    if (n > 0) {
+        hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NT), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, 1);
+        for (int c = 0; c < 3; ++c) {
+            const float ms = time_it([&] {
+                const dim3 pg(b->total[2]);
+                const size_t shm = sizeof(float4) * b->nred;
+                pcr_dispatch(threads[c], pcr_epl(threads[c], b->nred), [&](auto shape) {
+                    using S = decltype(shape);
+                    hipLaunchKernelGGL((kb_pcr<S::threads, S::epl>), pg, dim3(S::threads), shm, st, b->d_desc,
+                                       b->d_state, b->d_pre[2], n, 1);
+                });
+            });
+            if (ms < best) { best = ms; best_pnt = threads[c]; }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(hipGetLastError());
+    b->pnt = best_pnt;
+    b->total[0] = -1;  // the captured step is rebuilt with the chosen shapes
+    b->dirty = true;
+    std::memset(out, 0, sizeof *out);
+    out->stencil_rows = b->sy;
+    out->pcr_threads = b->pnt;
+    return WS_OK;
 }

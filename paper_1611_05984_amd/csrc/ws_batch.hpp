@@ -81,7 +81,8 @@ __device__ __forceinline__ int find_dom(const int *prefix, int ndom, int b) {
     return lo;
 }
 
-__global__ __launch_bounds__(64 * SWG) void kb_stencil(const BatchDesc *__restrict__ descs,
+template <int SYT>
+__global__ __launch_bounds__(64 * SWG) __attribute__((amdgpu_waves_per_eu(4))) void kb_stencil(const BatchDesc *__restrict__ descs,
                                                        const BatchState *__restrict__ states,
                                                        const int *__restrict__ prefix, int ndom, int p) {
     const int b = blockIdx.x, dm = find_dom(prefix, ndom, b);
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(64 * SWG) void kb_stencil(const BatchDesc *__restri
     if (v < 0) return;
     const int local = b - prefix[dm];
     const StencilArgs A = load_params(D.sa + v);
-    stencil_body(A, local % D.sgx, local / D.sgx);
+    stencil_body<SYT>(A, local % D.sgx, local / D.sgx);
 }
 
 __global__ __launch_bounds__(NT) void kb_reduce(const BatchDesc *__restrict__ descs,
@@ -106,7 +107,8 @@ __global__ __launch_bounds__(NT) void kb_reduce(const BatchDesc *__restrict__ de
     reduce_body(A, s, local % D.tgx, local / D.tgx);
 }
 
-__global__ __launch_bounds__(PCR_NT) void kb_pcr(const BatchDesc *__restrict__ descs,
+template <int PNT, int EPL>
+__global__ __launch_bounds__(PNT) void kb_pcr(const BatchDesc *__restrict__ descs,
                                                  const BatchState *__restrict__ states,
                                                  const int *__restrict__ prefix, int ndom, int p) {
     extern __shared__ float4 buf[];
@@ -118,10 +120,10 @@ __global__ __launch_bounds__(PCR_NT) void kb_pcr(const BatchDesc *__restrict__ d
     const int sys = b - prefix[dm], ny = load_params(&g->d.ny);
     if (sys < ny) {
         const int N = load_params(&g->d.nu);
-        pcr_solve(N, load_params(&g->redx) + (size_t)sys * N, load_params(&g->solx) + (size_t)sys * N, buf);
+        pcr_solve<PNT, EPL>(N, load_params(&g->redx) + (size_t)sys * N, load_params(&g->solx) + (size_t)sys * N, buf);
     } else {
         const int N = load_params(&g->d.nv);
-        pcr_solve(N, load_params(&g->redy) + (size_t)(sys - ny) * N, load_params(&g->soly) + (size_t)(sys - ny) * N,
+        pcr_solve<PNT, EPL>(N, load_params(&g->redy) + (size_t)(sys - ny) * N, load_params(&g->soly) + (size_t)(sys - ny) * N,
                   buf);
     }
 }

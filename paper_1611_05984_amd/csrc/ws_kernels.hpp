@@ -27,16 +27,21 @@
 
 namespace ws {
 
+// Field groups are consecutive fields of the workspace, fstride bytes apart:
+// a group is addressed by one base pointer plus k * fstride, which keeps the
+// kernel's uniform registers few (every field pointer would not fit in SGPRs).
 struct StencilArgs {
     Dom d;
-    const float *ein, *pin, *qin;      // estimate (the state itself for the predictor)
-    float *eout, *rx, *ry;             // new surface, U* - U*^n, V* - V*^n
-    float *hE, *hF, *hG, *hFs, *hGs;   // history level n (predictors write it)
-    const float *E1, *F1, *G1, *Fs1, *Gs1;  // level n-1
-    const float *E2, *F2, *G2, *Fs2, *Gs2;  // level n-2
-    float *Se, *SU, *SV;               // corrector bases (eta, U* and V* increments)
-    float dt, x0, x1, x2;              // step, F* extrapolation weights
-    int kind;                          // 0 Euler predictor, 1 AB3 predictor, 2 AM4 corrector
+    const float *in;     // estimate read (the state itself for the predictor): eta, P, Q
+    float *eout;         // new surface
+    float *rxy;          // U* - U*^n, V* - V*^n
+    float *h0;           // history level n (predictors write it): E, F, G, F*, G*
+    const float *h1;     // level n-1
+    const float *h2;     // level n-2
+    float *S;            // corrector bases: eta, U* and V* increments
+    unsigned fstride;    // bytes between consecutive fields of a group
+    float dt, x0, x1, x2;  // step, F* extrapolation weights
+    int kind;            // 0 Euler predictor, 1 AB3 predictor, 2 AM4 corrector
     int write_S;
 };
 
@@ -66,6 +71,23 @@ __device__ __forceinline__ void ghosts_body(const Dom &d, float *gh, double t, i
 
 __global__ void k_ghosts(Dom d, float *gh, double t) { ghosts_body(d, gh, t, blockIdx.x * blockDim.x + threadIdx.x); }
 
+// Field access by 32-bit byte offset from a uniform base pointer: the load or
+// store takes the base from SGPRs and the offset from one VGPR shared by all
+// fields (no 64-bit address arithmetic per access).
+__device__ __forceinline__ float ldo(const float *p, unsigned ob) {
+    return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(p) + ob);
+}
+__device__ __forceinline__ void sto(float *p, unsigned ob, float v) {
+    *reinterpret_cast<float *>(reinterpret_cast<char *>(p) + ob) = v;
+}
+__device__ __forceinline__ const float *ldp(const float *p, unsigned ob) {
+    return reinterpret_cast<const float *>(reinterpret_cast<const char *>(p) + ob);
+}
+
+// Rows per stencil strip: a template parameter (16, 32 or 64) chosen per grid
+// shape; taller strips spend less on the 4 warm-up rows, shorter ones give
+// small grids more workgroups.
+template <int SYT>
 __device__ __forceinline__ void stencil_body(const StencilArgs &A, int bx, int by) {
     const Dom &d = A.d;
     const int lane = threadIdx.x & 63;
@@ -75,12 +97,12 @@ __device__ __forceinline__ void stencil_body(const StencilArgs &A, int bx, int b
     const int col = c0 + lane;
     const int hcol = lane == 0 ? c0 - 1 : c0 + 64;  // halo column held by lanes 0 and 63
     const bool halo_lane = lane == 0 || lane == 63;
-    const int j0 = by * SY;
+    const int j0 = by * SYT;
     const float th = d.theta, g = d.g, eps = d.eps;
     const float rdx = d.rdx, rdy = d.rdy, Bd = d.Bd, B3 = d.Bd + 1.f / 3.f;
     // strips whose cells and corners (with halo) all lie inside the domain
     // load without boundary handling
-    const bool interior = c0 >= 1 && c0 + 64 <= d.nx - 1 && j0 >= 2 && j0 + SY + 1 <= d.ny - 1;
+    const bool interior = c0 >= 1 && c0 + 64 <= d.nx - 1 && j0 >= 2 && j0 + SYT + 1 <= d.ny - 1;
 
     // sliding windows (row index relative to the row r loaded this iteration)
     float e0 = 0.f, e1 = 0.f, e2 = 0.f, e3 = 0.f, e4 = 0.f;  // eta rows r-4 .. r
@@ -94,7 +116,34 @@ __device__ __forceinline__ void stencil_body(const StencilArgs &A, int bx, int b
     float Hs0 = 0.f, Hs1 = 0.f, Hs2 = 0.f;                   // flux through the south face of row r-2
     float Dcm = 0.f, Dc0 = 0.f;                              // cell depth D of rows r-3, r-2
 
-    for (int it = 0; it < SY + 4; ++it) {
+    const unsigned F1 = A.fstride, F2 = 2u * A.fstride, F3b = 3u * A.fstride, F4 = 4u * A.fstride;
+    const float *pin = ldp(A.in, F1), *qin = ldp(A.in, F2);
+    // row r + 1 is loaded while row r is computed
+    float ne = 0.f, np = 0.f, nq = 0.f, nhe = 0.f, nhp = 0.f, nhq = 0.f, nDl = 0.f, nDr = 0.f;
+    auto load_row = [&](int r) {
+        if (interior) {
+            const unsigned ob = (unsigned)(r * d.pitch + col) * 4u, ohb = (unsigned)(r * d.pitch + hcol) * 4u;
+            const unsigned ozb = (unsigned)(r * d.zpitch + col) * 4u;
+            ne = ldo(A.in, ob);
+            np = ldo(A.in, ob + F1);
+            nq = ldo(A.in, ob + F2);
+            if (halo_lane) {
+                nhe = ldo(A.in, ohb);
+                nhp = ldo(A.in, ohb + F1);
+                nhq = ldo(A.in, ohb + F2);
+            }
+            nDl = ldo(d.D, ozb);
+            nDr = ldo(d.D, ozb + 4u);
+        } else {
+            load_cell(d, A.in, pin, qin, col, r, ne, np, nq);
+            if (halo_lane) load_cell(d, A.in, pin, qin, hcol, r, nhe, nhp, nhq);
+            nDl = corner_D(d, col, r);
+            nDr = corner_D(d, col + 1, r);
+        }
+    };
+    load_row(j0 - 2);
+
+    for (int it = 0; it < SYT + 4; ++it) {
         const int r = j0 - 2 + it;
         e0 = e1; e1 = e2; e2 = e3; e3 = e4;
         p0 = p1; p1 = p2; p2 = p3;
@@ -102,24 +151,10 @@ __device__ __forceinline__ void stencil_body(const StencilArgs &A, int bx, int b
         he0 = he1; he1 = he2; hp0 = hp1; hp1 = hp2; hq0 = hq1; hq1 = hq2;
         Dl1 = Dl2; Dl2 = Dl3;
         Dr1 = Dr2; Dr2 = Dr3;
-        if (interior) {
-            const int o = r * d.pitch + col, oh = r * d.pitch + hcol, oz = r * d.zpitch + col;
-            e4 = A.ein[o];
-            p3 = A.pin[o];
-            q3 = A.qin[o];
-            if (halo_lane) {
-                he2 = A.ein[oh];
-                hp2 = A.pin[oh];
-                hq2 = A.qin[oh];
-            }
-            Dl3 = d.D[oz];
-            Dr3 = d.D[oz + 1];
-        } else {
-            load_cell(d, A.ein, A.pin, A.qin, col, r, e4, p3, q3);
-            if (halo_lane) load_cell(d, A.ein, A.pin, A.qin, hcol, r, he2, hp2, hq2);
-            Dl3 = corner_D(d, col, r);
-            Dr3 = corner_D(d, col + 1, r);
-        }
+        e4 = ne; p3 = np; q3 = nq;
+        he2 = nhe; hp2 = nhp; hq2 = nhq;
+        Dl3 = nDl; Dr3 = nDr;
+        if (it + 1 < SYT + 4) load_row(r + 1);
         // still-water depth D of the cell in row r-1
         const float Dcp = 0.25f * ((Dl2 + Dr2) + (Dl3 + Dr3));
         if (it < 2) {
@@ -139,16 +174,17 @@ __device__ __forceinline__ void stencil_body(const StencilArgs &A, int bx, int b
         if (it >= 4) {  // update row u = r - 2
             const int u = r - 2;
             const bool out = lane >= 1 && lane <= 62 && col < d.nx && u < d.ny;
-            const int o = u * d.pitch + col;
+            const unsigned o = (unsigned)(u * d.pitch + col) * 4u;  // byte offset (used by output lanes only)
             float E1v = 0.f, F1v = 0.f, G1v = 0.f, Fs1v = 0.f, Gs1v = 0.f, E2v = 0.f, F2v = 0.f, G2v = 0.f;
             float Fs2v = 0.f, Gs2v = 0.f, Sev = 0.f, SUv = 0.f, SVv = 0.f;
             if (out) {
                 if (A.kind == 1) {
-                    E1v = A.E1[o]; F1v = A.F1[o]; G1v = A.G1[o]; Fs1v = A.Fs1[o]; Gs1v = A.Gs1[o];
-                    E2v = A.E2[o]; F2v = A.F2[o]; G2v = A.G2[o];
-                    if (A.x2 != 0.f) { Fs2v = A.Fs2[o]; Gs2v = A.Gs2[o]; }
+                    E1v = ldo(A.h1, o); F1v = ldo(A.h1, o + F1); G1v = ldo(A.h1, o + F2);
+                    Fs1v = ldo(A.h1, o + F3b); Gs1v = ldo(A.h1, o + F4);
+                    E2v = ldo(A.h2, o); F2v = ldo(A.h2, o + F1); G2v = ldo(A.h2, o + F2);
+                    if (A.x2 != 0.f) { Fs2v = ldo(A.h2, o + F3b); Gs2v = ldo(A.h2, o + F4); }
                 } else if (A.kind == 2) {
-                    Sev = A.Se[o]; SUv = A.SU[o]; SVv = A.SV[o];
+                    Sev = ldo(A.S, o); SUv = ldo(A.S, o + F1); SVv = ldo(A.S, o + F2);
                 }
             }
             // cell and face still-water depths
@@ -217,9 +253,9 @@ __device__ __forceinline__ void stencil_body(const StencilArgs &A, int bx, int b
                 } else if (A.kind == 1) {
                     const float c12 = dt * (1.f / 12.f), c24 = dt * (1.f / 24.f);
                     if (A.write_S) {
-                        A.Se[o] = e2 + c24 * (19.f * E - 5.f * E1v + E2v);
-                        A.SU[o] = c24 * (19.f * F - 5.f * F1v + F2v) - Fs;
-                        A.SV[o] = c24 * (19.f * G - 5.f * G1v + G2v) - Gs;
+                        sto(A.S, o, e2 + c24 * (19.f * E - 5.f * E1v + E2v));
+                        sto(A.S, o + F1, c24 * (19.f * F - 5.f * F1v + F2v) - Fs);
+                        sto(A.S, o + F2, c24 * (19.f * G - 5.f * G1v + G2v) - Gs);
                     }
                     en = e2 + c12 * (23.f * E - 16.f * E1v + 5.f * E2v);
                     U = c12 * (23.f * F - 16.f * F1v + 5.f * F2v) + (A.x0 * Fs + A.x1 * Fs1v + A.x2 * Fs2v);
@@ -231,15 +267,15 @@ __device__ __forceinline__ void stencil_body(const StencilArgs &A, int bx, int b
                     V = SVv + c9 * G + Gs;
                 }
                 if (A.kind != 2) {
-                    A.hE[o] = E;
-                    A.hF[o] = F;
-                    A.hG[o] = G;
-                    A.hFs[o] = Fs;
-                    A.hGs[o] = Gs;
+                    sto(A.h0, o, E);
+                    sto(A.h0, o + F1, F);
+                    sto(A.h0, o + F2, G);
+                    sto(A.h0, o + F3b, Fs);
+                    sto(A.h0, o + F4, Gs);
                 }
-                A.eout[o] = fmaxf(en, -Dc);
-                A.rx[o] = U;
-                A.ry[o] = V;
+                sto(A.eout, o, fmaxf(en, -Dc));
+                sto(A.rxy, o, U);
+                sto(A.rxy, o + F1, V);
             }
         }
         hiy_prev = hiy;
@@ -251,7 +287,8 @@ __device__ __forceinline__ void stencil_body(const StencilArgs &A, int bx, int b
     }
 }
 
-__global__ __launch_bounds__(64 * SWG) void k_stencil(StencilArgs A) { stencil_body(A, blockIdx.x, blockIdx.y); }
+template <int SYT>
+__global__ __launch_bounds__(64 * SWG) __attribute__((amdgpu_waves_per_eu(4))) void k_stencil(StencilArgs A) { stencil_body<SYT>(A, blockIdx.x, blockIdx.y); }
 
 // ------------------------------------------------------------- solver parts
 struct SolveArgs {
@@ -458,18 +495,22 @@ __global__ __launch_bounds__(NT) void k_reduce(SolveArgs A) {
 // columns): each thread keeps its equations (k = tid + j * PCR_NT) in
 // registers; one LDS copy of the system (dynamic size N) is read, then
 // overwritten, per reduction level.
-constexpr int PCR_NT = 128;
-constexpr int PCR_EPL = NRED_MAX / PCR_NT;  // equations per thread at most
+// PNT threads per system (64, 128 or 256): a tuning choice between more
+// equations held per thread and more threads per barrier; EPL (a power of
+// two, PNT * EPL >= N) equations per thread at most, so the register array
+// is sized for the actual systems.
+constexpr int PCR_NT = 128;  // default
 // One reduced system of N equations (sub, diag, super, rhs) from src; solutions to dst.
+template <int PNT, int PCR_EPL>
 __device__ __forceinline__ void pcr_solve(int N, const float4 *src, float *dst, float4 *buf) {
     const int tid = threadIdx.x;
-    const int nmine = (N - tid + PCR_NT - 1) / PCR_NT;
+    const int nmine = (N - tid + PNT - 1) / PNT;
     float4 eq[PCR_EPL];
 #pragma unroll
     for (int j = 0; j < PCR_EPL; ++j)
         if (j < nmine) {
-            eq[j] = src[tid + j * PCR_NT];
-            buf[tid + j * PCR_NT] = eq[j];
+            eq[j] = src[tid + j * PNT];
+            buf[tid + j * PNT] = eq[j];
         }
     __syncthreads();
     const float4 id = make_float4(0.f, 1.f, 0.f, 0.f);
@@ -477,7 +518,7 @@ __device__ __forceinline__ void pcr_solve(int N, const float4 *src, float *dst, 
 #pragma unroll
         for (int j = 0; j < PCR_EPL; ++j)
             if (j < nmine) {
-                const int k = tid + j * PCR_NT;
+                const int k = tid + j * PNT;
                 const float4 e = eq[j];
                 const float4 m = k - st >= 0 ? buf[k - st] : id;
                 const float4 p = k + st < N ? buf[k + st] : id;
@@ -487,24 +528,26 @@ __device__ __forceinline__ void pcr_solve(int N, const float4 *src, float *dst, 
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < PCR_EPL; ++j)
-            if (j < nmine) buf[tid + j * PCR_NT] = eq[j];
+            if (j < nmine) buf[tid + j * PNT] = eq[j];
         __syncthreads();
     }
 #pragma unroll
     for (int j = 0; j < PCR_EPL; ++j)
-        if (j < nmine) dst[tid + j * PCR_NT] = eq[j].w / eq[j].y;
+        if (j < nmine) dst[tid + j * PNT] = eq[j].w / eq[j].y;
 }
 
 // System sys: rows 0..ny-1 (x direction), then columns.
+template <int PNT, int EPL>
 __device__ __forceinline__ void pcr_body(const SolveArgs &A, float4 *buf, int sys) {
     const Dom &d = A.d;
-    if (sys < d.ny) pcr_solve(d.nu, A.redx + (size_t)sys * d.nu, A.solx + (size_t)sys * d.nu, buf);
-    else pcr_solve(d.nv, A.redy + (size_t)(sys - d.ny) * d.nv, A.soly + (size_t)(sys - d.ny) * d.nv, buf);
+    if (sys < d.ny) pcr_solve<PNT, EPL>(d.nu, A.redx + (size_t)sys * d.nu, A.solx + (size_t)sys * d.nu, buf);
+    else pcr_solve<PNT, EPL>(d.nv, A.redy + (size_t)(sys - d.ny) * d.nv, A.soly + (size_t)(sys - d.ny) * d.nv, buf);
 }
 
-__global__ __launch_bounds__(PCR_NT) void k_pcr(SolveArgs A) {
+template <int PNT, int EPL>
+__global__ __launch_bounds__(PNT) void k_pcr(SolveArgs A) {
     extern __shared__ float4 buf[];
-    pcr_body(A, buf, blockIdx.x);
+    pcr_body<PNT, EPL>(A, buf, blockIdx.x);
 }
 
 __device__ __forceinline__ void expand_body(const SolveArgs &A, SolveTile &s, int bx, int by) {

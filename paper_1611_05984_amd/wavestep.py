@@ -42,6 +42,10 @@ class Boundary(C.Structure):
                 ("phase", C.POINTER(C.c_double)), ("ref_depth", C.c_double)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("stencil_rows", C.c_int32), ("pcr_threads", C.c_int32), ("reserved", C.c_int32 * 6)]
+
+
 class WaveStepError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__("wavestep status %d: %s" % (status, msg))
@@ -78,6 +82,11 @@ def lib():
             "ws_snapshot_bytes": (sz, [vp]),
             "ws_snapshot": (C.c_int, [vp, vp, sz, vp]),
             "ws_restore": (C.c_int, [vp, vp, sz, vp]),
+            "ws_get_tuning": (C.c_int, [vp, C.POINTER(Tuning)]),
+            "ws_set_tuning": (C.c_int, [vp, C.POINTER(Tuning)]),
+            "ws_batch_set_tuning": (C.c_int, [vp, C.POINTER(Tuning)]),
+            "ws_tune": (C.c_int, [vp, C.c_char_p, vp, C.POINTER(Tuning)]),
+            "ws_batch_tune": (C.c_int, [vp, vp, C.POINTER(Tuning)]),
             "ws_batch_workspace_bytes": (sz, [i32]),
             "ws_batch_create": (C.c_int, [i32, vp, sz, C.POINTER(vp)]),
             "ws_batch_destroy": (C.c_int, [vp]),
@@ -225,6 +234,22 @@ class Domain:
     def restore(self, buf, stream=None):
         _check(lib().ws_restore(self._h, _dptr(buf), buf.numel(), _stream(stream)), "ws_restore")
 
+    def tuning(self):
+        t = Tuning()
+        _check(lib().ws_get_tuning(self._h, C.byref(t)), "ws_get_tuning")
+        return t.stencil_rows, t.pcr_threads
+
+    def set_tuning(self, stencil_rows, pcr_threads):
+        t = Tuning(int(stencil_rows), int(pcr_threads))
+        _check(lib().ws_set_tuning(self._h, C.byref(t)), "ws_set_tuning")
+
+    def tune(self, cache_path=None, stream=None):
+        """Run the autotuner on this grid (or read its cache); returns the choice."""
+        t = Tuning()
+        path = cache_path.encode() if cache_path else None
+        _check(lib().ws_tune(self._h, path, _stream(stream), C.byref(t)), "ws_tune")
+        return t.stencil_rows, t.pcr_threads
+
     def profile(self, on=True):
         _check(lib().ws_profile_enable(self._h, 1 if on else 0), "ws_profile_enable")
 
@@ -270,6 +295,16 @@ class Batch:
     def detach(self, slot: int):
         _check(lib().ws_batch_detach(self._h, int(slot)), "ws_batch_detach")
         return self.domains.pop(int(slot))
+
+    def set_tuning(self, stencil_rows, pcr_threads):
+        t = Tuning(int(stencil_rows), int(pcr_threads))
+        _check(lib().ws_batch_set_tuning(self._h, C.byref(t)), "ws_batch_set_tuning")
+
+    def tune(self):
+        """Run the batch autotuner on the attached domains; returns the choice."""
+        t = Tuning()
+        _check(lib().ws_batch_tune(self._h, C.c_void_p(self.stream.cuda_stream), C.byref(t)), "ws_batch_tune")
+        return t.stencil_rows, t.pcr_threads
 
     def set_stop(self, slot, stop_step):
         """Do not advance the domain in `slot` past step `stop_step` (-1: no limit)."""

@@ -218,3 +218,47 @@ def test_snapshot_restore_continues_exactly():
     with pytest.raises(ws.WaveStepError) as e:
         other.restore(snap)
     assert e.value.status == ws.EINVAL
+
+
+def test_tunings_identical_results_and_autotuner(tmp_path):
+    """Every launch-shape choice gives the same bits; the autotuner leaves
+    the state untouched, picks a valid shape and reuses its cache."""
+    ws = _ws()
+    w = wl.config2(nx=300, ny=150, seed=11)
+    say("case: tunings on %s" % w.name)
+    ref = make(w)
+    ref.advance(30)
+    for sy, pn in [(8, 64), (16, 128), (24, 256), (48, 64), (64, 128), (32, 256)]:
+        d = make(w)
+        d.set_tuning(sy, pn)
+        assert d.tuning() == (sy, pn)
+        d.advance(30)
+        same(ref, d, "tuning %s" % ((sy, pn),))
+    d = make(w)
+    d.advance(30)
+    before = d.state_numpy()
+    cache = str(tmp_path / "tune.txt")
+    t = d.tune(cache)
+    assert t[0] in (8, 16, 24, 32, 48, 64) and t[1] in (64, 128, 256) and d.tuning() == t
+    after = d.state_numpy()
+    assert all(np.array_equal(x, y) for x, y in zip(before, after)) and d.query()[0] == 30
+    line = open(cache).read().split()
+    assert [int(v) for v in line] == [w.nx, w.ny, 2, 0, t[0], t[1]]
+    d2 = make(w)
+    assert d2.tune(cache) == t                     # read from the cache
+    d.advance(10)
+    ref.advance(10)
+    same(ref, d, "after tuning")
+    with pytest.raises(ws.WaveStepError):
+        d.set_tuning(40, 128)
+    B = ws.Batch(2)
+    b = make(w)
+    B.set_tuning(24, 64)
+    B.attach(b)
+    B.advance(20)
+    tb = B.tune()                                  # leaves the states alone
+    assert tb[0] in (8, 16, 24, 32, 48, 64) and tb[1] in (64, 128, 256)
+    B.advance(20)
+    B.sync()
+    same(ref, b, "batch tuned 24/64, then autotuned %s" % (tb,))
+    B.close()
