@@ -233,12 +233,17 @@ ws_status ws_batch_status(ws_batch *b, int32_t slot, int64_t *step, double *t, i
  * 64; taller strips repeat fewer warm-up rows, shorter ones give more
  * workgroups and a smaller last wave of workgroups).  pcr_threads: threads
  * per reduced tridiagonal system in the partitioned solve (64, 128 or 256:
- * equations held per thread versus threads per barrier).  Results do not
- * depend on the tuning (bitwise). */
+ * equations held per thread versus threads per barrier).  solver: the
+ * reduced systems by PCR (WS_SOLVE_PCR) or by the Thomas algorithm with one
+ * lane per system (WS_SOLVE_THOMAS: linear work, no barriers, a dependent
+ * chain per lane).  Rows and threads do not change results (bitwise); the
+ * solver changes only the rounding of the reduced solve. */
+enum { WS_SOLVE_PCR = 0, WS_SOLVE_THOMAS = 1 };  /* reduced-system strategy */
 typedef struct {
     int32_t stencil_rows;
     int32_t pcr_threads;
-    int32_t reserved[6];
+    int32_t solver;
+    int32_t reserved[5];
 } ws_tuning;
 ws_status ws_get_tuning(const ws_domain *d, ws_tuning *out);
 ws_status ws_set_tuning(ws_domain *d, const ws_tuning *t);

@@ -67,7 +67,7 @@ struct ws_domain {
     int64_t stop;                  // batch step limit (-1: none)
     int bhealth;                   // health word as of the last batch sync
     bool vdirty;                   // pass argument tables must be rewritten
-    int sy, pnt;                   // tuning: stencil rows per strip, PCR threads per system
+    int sy, pnt, solver;           // tuning: stencil rows per strip, PCR threads per system, reduced solver
     size_t fstride;                // bytes between consecutive fields
     StencilArgs *vsa;              // pass argument tables (device), batch use only
     SolveArgs *vso;
@@ -370,6 +370,7 @@ extern "C" ws_status ws_domain_init(const ws_grid *g, const float *z_corners_dev
     d->vdirty = true;
     d->sy = SY;
     d->pnt = PCR_NT;
+    d->solver = WS_SOLVE_PCR;
     d->fstride = L.field;
     for (int s = 0; s < 4; ++s) { d->side_type[s] = WS_BC_SOLID; d->side_width[s] = 2; }
     hipStream_t st = (hipStream_t)stream;
@@ -779,6 +780,17 @@ static bool has_makers(const ws_domain *d) {
     return false;
 }
 
+// The reduced row and column systems, by the domain's strategy.
+static void launch_reduced(const ws_domain *d, hipStream_t st, const SolveArgs &so) {
+    if (d->solver == WS_SOLVE_THOMAS) {
+        const int waves = (d->g.ny + 63) / 64 + (d->g.nx + 63) / 64;
+        hipLaunchKernelGGL(k_thomas, dim3(waves), dim3(64), 0, st, so);
+    } else {
+        const int nred = d->nu > d->nv ? d->nu : d->nv;
+        launch_pcr(d->pnt, nred, d->g.ny + d->g.nx, st, so);
+    }
+}
+
 static ws_status run_pass(ws_domain *d, const StencilArgs &sa, const SolveArgs &so, hipStream_t st) {
     {
         ProfScope p(d, st, sa.kind == 2 ? WS_K_CORRECTOR : WS_K_PREDICTOR);
@@ -790,8 +802,7 @@ static ws_status run_pass(ws_domain *d, const StencilArgs &sa, const SolveArgs &
     }
     {
         ProfScope p(d, st, WS_K_PCR);
-        const int nred = d->nu > d->nv ? d->nu : d->nv;
-        launch_pcr(d->pnt, nred, d->g.ny + d->g.nx, st, so);
+        launch_reduced(d, st, so);
     }
     {
         ProfScope p(d, st, WS_K_EXPAND);
@@ -862,7 +873,7 @@ struct ws_batch {
     hipGraphExec_t exec = nullptr;
     hipStream_t gstream = nullptr;
     hipStream_t last = nullptr;
-    int sy = SY, pnt = PCR_NT;           // tuning shared by all domains of the batch
+    int sy = SY, pnt = PCR_NT, solver = WS_SOLVE_PCR;  // tuning shared by all domains of the batch
 };
 
 static size_t batch_layout(int max, size_t *o_state, size_t *o_pre) {
@@ -977,7 +988,7 @@ static ws_status batch_upload(ws_batch *b) {
         const BatchDesc &D = desc[k];
         pre[0][k + 1] = pre[0][k] + D.sgx * D.sgy;
         pre[1][k + 1] = pre[1][k] + D.tgx * D.tgy;
-        pre[2][k + 1] = pre[2][k] + D.nsys;
+        pre[2][k + 1] = pre[2][k] + (b->solver == WS_SOLVE_THOMAS ? (D.d.ny + 63) / 64 + (D.d.nx + 63) / 64 : D.nsys);
         pre[3][k + 1] = pre[3][k] + (D.makers ? (8 * D.d.gl + 255) / 256 : 0);
         maxK = D.K > maxK ? D.K : maxK;
         const int nr = d->nu > d->nv ? d->nu : d->nv;
@@ -1014,11 +1025,14 @@ static ws_status batch_step(ws_batch *b, hipStream_t st) {
 #undef L4
         hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NT), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, p);
         const size_t shm = sizeof(float4) * b->nred;
-        pcr_dispatch(b->pnt, pcr_epl(b->pnt, b->nred), [&](auto shape) {
-            using S = decltype(shape);
-            hipLaunchKernelGGL((kb_pcr<S::threads, S::epl>), pg, dim3(S::threads), shm, st, b->d_desc, b->d_state,
-                               b->d_pre[2], n, p);
-        });
+        if (b->solver == WS_SOLVE_THOMAS)
+            hipLaunchKernelGGL(kb_thomas, pg, dim3(64), 0, st, b->d_desc, b->d_state, b->d_pre[2], n, p);
+        else
+            pcr_dispatch(b->pnt, pcr_epl(b->pnt, b->nred), [&](auto shape) {
+                using S = decltype(shape);
+                hipLaunchKernelGGL((kb_pcr<S::threads, S::epl>), pg, dim3(S::threads), shm, st, b->d_desc,
+                                   b->d_state, b->d_pre[2], n, p);
+            });
         hipLaunchKernelGGL(kb_expand, dim3(b->total[1]), dim3(NT), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, p);
     }
     hipLaunchKernelGGL(kb_finish, dim3((n + 255) / 256), dim3(256), 0, st, b->d_desc, b->d_state, n);
@@ -1160,7 +1174,8 @@ extern "C" ws_status ws_batch_sync(ws_batch *b, void *stream) {
 static bool tuning_ok(const ws_tuning *t) {
     return t && (t->stencil_rows == 8 || t->stencil_rows == 16 || t->stencil_rows == 24 ||
                  t->stencil_rows == 32 || t->stencil_rows == 48 || t->stencil_rows == 64) &&
-           (t->pcr_threads == 64 || t->pcr_threads == 128 || t->pcr_threads == 256);
+           (t->pcr_threads == 64 || t->pcr_threads == 128 || t->pcr_threads == 256) &&
+           (t->solver == WS_SOLVE_PCR || t->solver == WS_SOLVE_THOMAS);
 }
 
 extern "C" ws_status ws_get_tuning(const ws_domain *d, ws_tuning *out) {
@@ -1168,6 +1183,7 @@ extern "C" ws_status ws_get_tuning(const ws_domain *d, ws_tuning *out) {
     std::memset(out, 0, sizeof *out);
     out->stencil_rows = d->sy;
     out->pcr_threads = d->pnt;
+    out->solver = d->solver;
     return WS_OK;
 }
 
@@ -1175,14 +1191,16 @@ extern "C" ws_status ws_set_tuning(ws_domain *d, const ws_tuning *t) {
     if (!d || !tuning_ok(t)) return fail(WS_EINVAL, "ws_set_tuning: bad tuning");
     d->sy = t->stencil_rows;
     d->pnt = t->pcr_threads;
+    d->solver = t->solver;
     return WS_OK;
 }
 
 extern "C" ws_status ws_batch_set_tuning(ws_batch *b, const ws_tuning *t) {
     if (!b || !tuning_ok(t)) return fail(WS_EINVAL, "ws_batch_set_tuning: bad tuning");
-    if (b->sy != t->stencil_rows || b->pnt != t->pcr_threads) {
+    if (b->sy != t->stencil_rows || b->pnt != t->pcr_threads || b->solver != t->solver) {
         b->sy = t->stencil_rows;
         b->pnt = t->pcr_threads;
+        b->solver = t->solver;
         b->dirty = true;
         b->total[0] = -1;  // launch shapes change: the captured step is rebuilt
     }
@@ -1193,12 +1211,13 @@ static bool cache_lookup(const char *path, const ws_grid &g, ws_tuning *t) {
     if (!path) return false;
     FILE *f = std::fopen(path, "r");
     if (!f) return false;
-    int nx, ny, k, m, sy, pn;
+    int nx, ny, k, m, sy, pn, so;
     bool hit = false;
-    while (std::fscanf(f, "%d %d %d %d %d %d", &nx, &ny, &k, &m, &sy, &pn) == 6) {
+    while (std::fscanf(f, "%d %d %d %d %d %d %d", &nx, &ny, &k, &m, &sy, &pn, &so) == 7) {
         if (nx == g.nx && ny == g.ny && k == g.n_corr && m == g.model) {
             t->stencil_rows = sy;
             t->pcr_threads = pn;
+            t->solver = so;
             hit = tuning_ok(t);
         }
     }
@@ -1238,6 +1257,7 @@ extern "C" ws_status ws_tune(ws_domain *d, const char *cache_path, void *stream,
     float best_s = 1e30f, best_p = 1e30f;
     best.stencil_rows = SY;
     best.pcr_threads = PCR_NT;
+    best.solver = WS_SOLVE_PCR;
     const int rows[6] = {8, 16, 24, 32, 48, 64};
     for (int c = 0; c < 6; ++c) {
         const dim3 grid = strips_for(d, rows[c]);
@@ -1262,7 +1282,24 @@ extern "C" ws_status ws_tune(ws_domain *d, const char *cache_path, void *stream,
         HIPCHK(hipEventSynchronize(e1));
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best_p) { best_p = ms; best.pcr_threads = threads[c]; }
+        if (ms < best_p) { best_p = ms; best.pcr_threads = threads[c]; best.solver = WS_SOLVE_PCR; }
+    }
+    {
+        const int waves = (d->g.ny + 63) / 64 + (d->g.nx + 63) / 64;
+        hipLaunchKernelGGL(k_reduce, tiles(d), dim3(NT), 0, st, so);  // the sweep overwrites the equations
+        hipLaunchKernelGGL(k_thomas, dim3(waves), dim3(64), 0, st, so);
+        float total = 0.f;
+        for (int k = 0; k < reps; ++k) {
+            hipLaunchKernelGGL(k_reduce, tiles(d), dim3(NT), 0, st, so);
+            HIPCHK(hipEventRecord(e0, st));
+            hipLaunchKernelGGL(k_thomas, dim3(waves), dim3(64), 0, st, so);
+            HIPCHK(hipEventRecord(e1, st));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            total += ms;
+        }
+        if (total < best_p) { best_p = total; best.solver = WS_SOLVE_THOMAS; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1270,8 +1307,8 @@ extern "C" ws_status ws_tune(ws_domain *d, const char *cache_path, void *stream,
     if (cache_path) {
         FILE *f = std::fopen(cache_path, "a");
         if (f) {
-            std::fprintf(f, "%d %d %d %d %d %d\n", d->g.nx, d->g.ny, d->g.n_corr, d->g.model, best.stencil_rows,
-                         best.pcr_threads);
+            std::fprintf(f, "%d %d %d %d %d %d %d\n", d->g.nx, d->g.ny, d->g.n_corr, d->g.model, best.stencil_rows,
+                         best.pcr_threads, best.solver);
             std::fclose(f);
         }
     }
@@ -1303,7 +1340,8 @@ extern "C" ws_status ws_batch_tune(ws_batch *b, void *stream, ws_tuning *out) {
         return ms;
     };
     const int rows[6] = {8, 16, 24, 32, 48, 64}, threads[3] = {64, 128, 256};
-    int best_sy = b->sy, best_pnt = b->pnt;
+    int best_sy = b->sy, best_pnt = b->pnt, best_solver = WS_SOLVE_PCR;
+    b->solver = WS_SOLVE_PCR;  // the PCR trials use the PCR prefix table
     float best = 1e30f;
     for (int c = 0; c < 6; ++c) {
         b->sy = rows[c];
@@ -1338,15 +1376,33 @@ extern "C" ws_status ws_batch_tune(ws_batch *b, void *stream, ws_tuning *out) {
             });
             if (ms < best) { best = ms; best_pnt = threads[c]; }
         }
+        // lane-per-system Thomas (its prefix table differs: rebuilt for the trial)
+        b->solver = WS_SOLVE_THOMAS;  // trial
+        b->dirty = true;
+        if ((r = batch_upload(b)) != WS_OK) return r;
+        float total = 0.f;
+        for (int k = 0; k < 4; ++k) {
+            hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NT), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, 1);
+            (void)hipEventRecord(e0, st);
+            hipLaunchKernelGGL(kb_thomas, dim3(b->total[2]), dim3(64), 0, st, b->d_desc, b->d_state, b->d_pre[2], n, 1);
+            (void)hipEventRecord(e1, st);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (k > 0) total += ms;
+        }
+        best_solver = total < best ? WS_SOLVE_THOMAS : WS_SOLVE_PCR;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     HIPCHK(hipGetLastError());
     b->pnt = best_pnt;
+    b->solver = best_solver;
     b->total[0] = -1;  // the captured step is rebuilt with the chosen shapes
     b->dirty = true;
     std::memset(out, 0, sizeof *out);
     out->stencil_rows = b->sy;
     out->pcr_threads = b->pnt;
+    out->solver = b->solver;
     return WS_OK;
 }

@@ -141,6 +141,27 @@ __global__ __launch_bounds__(NT) void kb_expand(const BatchDesc *__restrict__ de
     expand_body(A, s, local % D.tgx, local / D.tgx);
 }
 
+// Reduced systems by lane-per-system Thomas: workgroup (one wave) b - prefix
+// of a domain takes row systems first, then column systems.
+__global__ __launch_bounds__(64) void kb_thomas(const BatchDesc *__restrict__ descs,
+                                                const BatchState *__restrict__ states,
+                                                const int *__restrict__ prefix, int ndom, int p) {
+    const int b = blockIdx.x, dm = find_dom(prefix, ndom, b);
+    const BatchDesc &D = descs[dm];
+    const int v = variant(D, states[dm], p);
+    if (v < 0) return;
+    const SolveArgs *g = D.so + v;
+    const int wave = b - prefix[dm], lane = threadIdx.x;
+    const int ny = load_params(&g->d.ny), nx = load_params(&g->d.nx), xw = (ny + 63) / 64;
+    if (wave < xw) {
+        const int sys = wave * 64 + lane, N = load_params(&g->d.nu);
+        if (sys < ny) thomas_lane(N, load_params(&g->redx) + (size_t)sys * N, load_params(&g->solx) + (size_t)sys * N);
+    } else {
+        const int sys = (wave - xw) * 64 + lane, N = load_params(&g->d.nv);
+        if (sys < nx) thomas_lane(N, load_params(&g->redy) + (size_t)sys * N, load_params(&g->soly) + (size_t)sys * N);
+    }
+}
+
 // Wave-maker ghosts of t^n (which = 0) and t^{n+1} (which = 1); 256 threads
 // per block, 8 gl threads per domain with wave makers.
 __global__ void kb_ghosts(const BatchDesc *descs, const BatchState *states, const int *prefix, int ndom,

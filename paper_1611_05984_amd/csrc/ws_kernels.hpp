@@ -491,6 +491,47 @@ __global__ __launch_bounds__(NT) void k_reduce(SolveArgs A) {
     reduce_body(A, s, blockIdx.x, blockIdx.y);
 }
 
+// The reduced systems by the Thomas algorithm, one lane per system: lanes of
+// a wave take consecutive systems (rows first, then columns; a wave never
+// mixes the two), each walks its own contiguous equations, so a wave's loads
+// touch 64 lines whose next equations stay cached.  The forward sweep keeps
+// its modified super-diagonal and right-hand side in the equation's own
+// (z, w) slots, which the backward sweep reads back.  Work is linear in N
+// with no barriers; the sweep is a dependent chain of N steps per lane.
+__device__ __forceinline__ void thomas_lane(int N, float4 *eq, float *x) {
+    float cp = 0.f, dp = 0.f;
+    for (int k = 0; k < N; ++k) {
+        const float4 e = eq[k];
+        const float inv = frcp(e.y - e.x * cp);
+        cp = e.z * inv;
+        dp = (e.w - e.x * dp) * inv;
+        reinterpret_cast<float2 *>(eq + k)[1] = make_float2(cp, dp);
+    }
+    float v = dp;
+    x[N - 1] = v;
+    for (int k = N - 2; k >= 0; --k) {
+        const float2 cd = reinterpret_cast<const float2 *>(eq + k)[1];
+        v = cd.y - cd.x * v;
+        x[k] = v;
+    }
+}
+
+// Waves 0 .. xw-1 take the row systems (xw = ceil(ny / 64)), the rest the
+// column systems.
+__device__ __forceinline__ void thomas_body(const SolveArgs &A, int wave, int lane) {
+    const Dom &d = A.d;
+    const int xw = (d.ny + 63) / 64;
+    if (wave < xw) {
+        const int sys = wave * 64 + lane;
+        if (sys < d.ny) thomas_lane(d.nu, A.redx + (size_t)sys * d.nu, A.solx + (size_t)sys * d.nu);
+    } else {
+        const int sys = (wave - xw) * 64 + lane;
+        if (sys < d.nx) thomas_lane(d.nv, A.redy + (size_t)sys * d.nv, A.soly + (size_t)sys * d.nv);
+    }
+}
+
+__global__ __launch_bounds__(64) void k_thomas(SolveArgs A) { thomas_body(A, blockIdx.x, threadIdx.x); }
+
 // Parallel cyclic reduction of one reduced system (rows first, then
 // columns): each thread keeps its equations (k = tid + j * PCR_NT) in
 // registers; one LDS copy of the system (dynamic size N) is read, then

@@ -23,6 +23,7 @@ WEST, EAST, SOUTH, NORTH = 0, 1, 2, 3
 SOLID, SPONGE, WAVES = 0, 1, 2
 EDIT_WATER, EDIT_TERRAIN = 0, 1
 READ_W, READ_H = 0, 1
+SOLVE_PCR, SOLVE_THOMAS = 0, 1
 K_PREDICTOR, K_CORRECTOR, K_REDUCE, K_PCR, K_EXPAND, K_COUNT = 0, 1, 2, 3, 4, 5
 KERNEL_NAMES = ("k_stencil[predictor]", "k_stencil[corrector]", "k_reduce", "k_pcr", "k_expand")
 
@@ -43,7 +44,8 @@ class Boundary(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("stencil_rows", C.c_int32), ("pcr_threads", C.c_int32), ("reserved", C.c_int32 * 6)]
+    _fields_ = [("stencil_rows", C.c_int32), ("pcr_threads", C.c_int32), ("solver", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
 
 
 class WaveStepError(RuntimeError):
@@ -235,12 +237,13 @@ class Domain:
         _check(lib().ws_restore(self._h, _dptr(buf), buf.numel(), _stream(stream)), "ws_restore")
 
     def tuning(self):
+        """(stencil rows, PCR threads, reduced solver) of this domain."""
         t = Tuning()
         _check(lib().ws_get_tuning(self._h, C.byref(t)), "ws_get_tuning")
-        return t.stencil_rows, t.pcr_threads
+        return t.stencil_rows, t.pcr_threads, t.solver
 
-    def set_tuning(self, stencil_rows, pcr_threads):
-        t = Tuning(int(stencil_rows), int(pcr_threads))
+    def set_tuning(self, stencil_rows, pcr_threads, solver=SOLVE_PCR):
+        t = Tuning(int(stencil_rows), int(pcr_threads), int(solver))
         _check(lib().ws_set_tuning(self._h, C.byref(t)), "ws_set_tuning")
 
     def tune(self, cache_path=None, stream=None):
@@ -248,7 +251,7 @@ class Domain:
         t = Tuning()
         path = cache_path.encode() if cache_path else None
         _check(lib().ws_tune(self._h, path, _stream(stream), C.byref(t)), "ws_tune")
-        return t.stencil_rows, t.pcr_threads
+        return t.stencil_rows, t.pcr_threads, t.solver
 
     def profile(self, on=True):
         _check(lib().ws_profile_enable(self._h, 1 if on else 0), "ws_profile_enable")
@@ -296,15 +299,15 @@ class Batch:
         _check(lib().ws_batch_detach(self._h, int(slot)), "ws_batch_detach")
         return self.domains.pop(int(slot))
 
-    def set_tuning(self, stencil_rows, pcr_threads):
-        t = Tuning(int(stencil_rows), int(pcr_threads))
+    def set_tuning(self, stencil_rows, pcr_threads, solver=SOLVE_PCR):
+        t = Tuning(int(stencil_rows), int(pcr_threads), int(solver))
         _check(lib().ws_batch_set_tuning(self._h, C.byref(t)), "ws_batch_set_tuning")
 
     def tune(self):
         """Run the batch autotuner on the attached domains; returns the choice."""
         t = Tuning()
         _check(lib().ws_batch_tune(self._h, C.c_void_p(self.stream.cuda_stream), C.byref(t)), "ws_batch_tune")
-        return t.stencil_rows, t.pcr_threads
+        return t.stencil_rows, t.pcr_threads, t.solver
 
     def set_stop(self, slot, stop_step):
         """Do not advance the domain in `slot` past step `stop_step` (-1: no limit)."""

@@ -231,21 +231,30 @@ def test_tunings_identical_results_and_autotuner(tmp_path):
     for sy, pn in [(8, 64), (16, 128), (24, 256), (48, 64), (64, 128), (32, 256)]:
         d = make(w)
         d.set_tuning(sy, pn)
-        assert d.tuning() == (sy, pn)
+        assert d.tuning() == (sy, pn, ws.SOLVE_PCR)
         d.advance(30)
         same(ref, d, "tuning %s" % ((sy, pn),))
+    # the lane-per-system Thomas solve of the reduced systems rounds
+    # differently from PCR: equal within the parity tolerance of the solve
+    th = make(w)
+    th.set_tuning(16, 128, ws.SOLVE_THOMAS)
+    th.advance(30)
+    for x, y in zip(ref.state_numpy(), th.state_numpy()):
+        assert np.abs(x - y).max() <= 1e-6 * max(1.0, np.abs(x).max())
     d = make(w)
     d.advance(30)
     before = d.state_numpy()
     cache = str(tmp_path / "tune.txt")
     t = d.tune(cache)
-    assert t[0] in (8, 16, 24, 32, 48, 64) and t[1] in (64, 128, 256) and d.tuning() == t
+    assert t[0] in (8, 16, 24, 32, 48, 64) and t[1] in (64, 128, 256) and t[2] in (0, 1)
+    assert d.tuning() == t
     after = d.state_numpy()
     assert all(np.array_equal(x, y) for x, y in zip(before, after)) and d.query()[0] == 30
     line = open(cache).read().split()
-    assert [int(v) for v in line] == [w.nx, w.ny, 2, 0, t[0], t[1]]
+    assert [int(v) for v in line] == [w.nx, w.ny, 2, 0, t[0], t[1], t[2]]
     d2 = make(w)
     assert d2.tune(cache) == t                     # read from the cache
+    d.set_tuning(t[0], t[1], ws.SOLVE_PCR)        # bitwise comparable with the reference
     d.advance(10)
     ref.advance(10)
     same(ref, d, "after tuning")
@@ -257,8 +266,19 @@ def test_tunings_identical_results_and_autotuner(tmp_path):
     B.attach(b)
     B.advance(20)
     tb = B.tune()                                  # leaves the states alone
-    assert tb[0] in (8, 16, 24, 32, 48, 64) and tb[1] in (64, 128, 256)
+    assert tb[0] in (8, 16, 24, 32, 48, 64) and tb[1] in (64, 128, 256) and tb[2] in (0, 1)
+    B.set_tuning(tb[0], tb[1], ws.SOLVE_PCR)
     B.advance(20)
     B.sync()
     same(ref, b, "batch tuned 24/64, then autotuned %s" % (tb,))
+    th2 = make(w)                                  # batched Thomas equals single-domain Thomas
+    th2b = make(w)
+    th2.set_tuning(16, 128, ws.SOLVE_THOMAS)
+    B.detach(0)
+    B.set_tuning(16, 128, ws.SOLVE_THOMAS)
+    B.attach(th2b)
+    B.advance(30)
+    th2.advance(30)
+    B.sync()
+    same(th2, th2b, "batched Thomas")
     B.close()
