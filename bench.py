@@ -21,6 +21,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TUNING_CACHE = os.path.join(ROOT, "paper_1611_05984_amd", "tuning_cache.txt")
 
 # Compulsory FP32 words per cell of each kernel class (reads + writes), for
 # the default configuration (linear F* extrapolation, two correctors):
@@ -51,6 +52,8 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a 256 MiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--retune", action="store_true",
+                    help="measure the launch shapes instead of reading the tuning cache")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-vs-plain ensemble measurement")
     ap.add_argument("--ens-steps", type=int, default=30, help="timed steps of the ensemble runs")
@@ -211,7 +214,9 @@ def main():
                            side.phase or None)
     print("bench: %s ready, warmup %d steps" % (w.name, args.warmup), file=sys.stderr, flush=True)
     D.advance(args.warmup)
-    tuning = D.tune()                  # autotuner: launch shapes for this grid
+    # autotuner: launch shapes for this grid, read from its cache when this
+    # shape was measured before (the cache file ships with the package)
+    tuning = D.tune(cache_path=None if args.retune else TUNING_CACHE)
     print("bench: tuned %s" % (tuning,), file=sys.stderr, flush=True)
     D.advance(2)
     torch.cuda.synchronize()
@@ -236,8 +241,10 @@ def main():
     tot = sum(ms for ms, n in prof.values())
     fsum = {f: (sum(prof[c][0] for c in cs), sum(prof[c][1] for c in cs),
                 sum(ALG_WORDS[c] * prof[c][1] for c in cs)) for f, cs in FUNCS.items()}
-    dom_name = max(fsum, key=lambda f: fsum[f][0])
-    dom_ms, dom_n, dom_words = fsum[dom_name]
+    dom_func = max(fsum, key=lambda f: fsum[f][0])
+    # kernel symbol as the profiler names it (template instance of the tuned shape)
+    dom_name = {"k_stencil": "k_stencil<%d>" % tuning[0]}.get(dom_func, dom_func)
+    dom_ms, dom_n, dom_words = fsum[dom_func]
     avg_s = dom_ms / dom_n / 1e3
     alg_bytes = dom_words / dom_n * 4.0 * cells
     achieved = alg_bytes / avg_s / 1e9
@@ -303,7 +310,7 @@ def main():
 def _source_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("ws_device.hpp", "ws_kernels.hpp", "wavestep.hip"):
+    for f in ("ws_device.hpp", "ws_kernels.hpp", "ws_batch.hpp", "wavestep.hip"):
         h.update(open(os.path.join(ROOT, "paper_1611_05984_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -54,14 +54,41 @@ def calib(values):
 
 
 def short(name):
-    return name.split("(")[0].replace("ws::", "")
+    """Kernel name without return type, namespace and parameter list."""
+    n = name[5:] if name.startswith("void ") else name
+    return n.split("(")[0].replace("ws::", "")
 
 
 def source_hash(root):
     h = hashlib.sha256()
-    for f in ("ws_device.hpp", "ws_kernels.hpp", "wavestep.hip"):
+    for f in ("ws_device.hpp", "ws_kernels.hpp", "ws_batch.hpp", "wavestep.hip"):
         h.update(open(os.path.join(root, "paper_1611_05984_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
+
+
+VALU_PEAK = 256 * 4 * 16 * 2.4e9  # lane-instructions/s: CUs x SIMDs x lanes x clock (non-packed FP32)
+
+
+def sq_table(sq_db, trace_db, cells):
+    """Per kernel: VALU instructions per dispatch, lane-instructions per cell
+    and VALU issue utilisation over the kernel's average traced duration."""
+    per = defaultdict(lambda: defaultdict(list))
+    for name, counter, v in _q(sq_db, "select kernel_name, counter_name, value from counters_collection"):
+        per[short(name)][counter].append(float(v))
+    avg_us = {short(n): a for n, _, _, a, _ in trace_table(trace_db)}
+    lines = ["VALU issue peak (non-packed FP32): 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = %.1fe12 "
+             "lane-instructions/s" % (VALU_PEAK / 1e12),
+             "%-20s %13s %15s %11s %10s" % ("kernel", "VALU/disp", "lane-instr/cell", "avg_us", "VALU util")]
+    for k in sorted(per):
+        if k not in avg_us or "SQ_INSTS_VALU" not in per[k]:
+            continue
+        vals = per[k]["SQ_INSTS_VALU"]
+        valu = sum(vals) / len(vals)
+        lane = valu * 64
+        util = lane / (avg_us[k] * 1e-6) / VALU_PEAK
+        lines.append("%-20s %13.4g %15.1f %11.1f %9.0f%%" % (k, valu, lane / cells if cells else 0, avg_us[k],
+                                                             100 * util))
+    return lines
 
 
 def main():
@@ -73,7 +100,9 @@ def main():
     ap.add_argument("--out")
     ap.add_argument("--traffic-json")
     ap.add_argument("--command", default="")
-    ap.add_argument("--kernel", default="k_stencil")
+    ap.add_argument("--kernel", default="k_stencil<16>",
+                    help="kernel (as the trace names it, without namespace) whose traffic goes to --traffic-json")
+    ap.add_argument("--sq", help="database of a rocprofv3 --pmc SQ_INSTS_VALU ... run (VALU table)")
     ap.add_argument("--skip", type=int, default=2,
                     help="leading dispatches per kernel left out of the averages (Euler start-up)")
     a = ap.parse_args()
@@ -91,7 +120,7 @@ def main():
         lines.append("HBM bytes per dispatch (FETCH_SIZE x %.3f, WRITE_SIZE x %.3f; factors from the "
                      "%d-byte device copy)" % (fs or 0, wsc or 0, COPY_BYTES))
         for name in sorted(fv):
-            if not name.startswith("ws::"):
+            if "ws::" not in name.split("(")[0]:
                 continue
             rd = [v * fs for v in fv[name]][a.skip:]
             wr = [v * wsc for v in wv.get(name, [])][a.skip:]
@@ -104,6 +133,9 @@ def main():
             lines.append(txt)
             traffic[short(name)] = {"read": avg_r, "write": avg_w, "dispatches": n,
                                     "per_dispatch": per}
+    if a.sq:
+        lines.append("")
+        lines.extend(sq_table(a.sq, a.trace, a.cells))
     text = "\n".join(lines)
     print(text)
     if a.out:
