@@ -749,6 +749,21 @@ static void pass_args(const ws_domain *d, const Dom &m, bool euler, int cur, int
     sa.h2 = d->hist[n2][0];
     sa.S = d->S[0];
     sa.fstride = (unsigned)d->fstride;
+    {
+        const double rx = 1.0 / g.dx, ry = 1.0 / g.dy;
+        sa.hx = (float)(0.5 * rx);
+        sa.hy = (float)(0.5 * ry);
+        sa.sxx = (float)(rx * rx);
+        sa.syy = (float)(ry * ry);
+        sa.cxy = (float)(0.25 * rx * ry);
+        sa.cxxx = (float)(0.5 * rx * rx * rx);
+        sa.cyyy = (float)(0.5 * ry * ry * ry);
+        sa.cxyy = (float)(0.5 * rx * ry * ry);
+        sa.cxxy = (float)(0.5 * rx * rx * ry);
+        sa.gx = (float)(g.g * rx);
+        sa.gy = (float)(g.g * ry);
+        sa.Bg = (float)(g.Bcoef * g.g);
+    }
     sa.dt = (float)g.dt;
     sa.x0 = sa.x1 = sa.x2 = 0.f;
     if (g.fstar_extrap == 2) { sa.x0 = 2.f; sa.x1 = -3.f; sa.x2 = 1.f; }

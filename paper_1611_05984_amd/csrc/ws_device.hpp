@@ -149,6 +149,15 @@ __device__ __forceinline__ float shr1(float v, float old) {
 __device__ __forceinline__ float shl1(float v, float old) {
     return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), 0x130, 0xf, 0xf, false));
 }
+// The same shifts where the edge lane's result is never used (it belongs to
+// a halo lane): the vacated lane reads 0 (bound_ctrl), so the shift is one
+// DPP move with no copy of an "old" value first.
+__device__ __forceinline__ float shr1z(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float shl1z(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
+}
 
 struct F3 { float e, n, t; };  // surface, normal and tangential discharge at a face
 

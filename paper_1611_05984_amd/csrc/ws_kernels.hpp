@@ -40,6 +40,10 @@ struct StencilArgs {
     const float *h2;     // level n-2
     float *S;            // corrector bases: eta, U* and V* increments
     unsigned fstride;    // bytes between consecutive fields of a group
+    // grid-spacing factors of the difference formulas, premultiplied:
+    // hx = 1/(2dx), sxx = 1/dx^2, cxy = 1/(4 dx dy), cxxx = 1/(2 dx^3),
+    // cxyy = 1/(2 dx dy^2), gx = g/dx, Bg = B g (y analogues likewise)
+    float hx, hy, sxx, syy, cxy, cxxx, cyyy, cxyy, cxxy, gx, gy, Bg;
     float dt, x0, x1, x2;  // step, F* extrapolation weights
     int kind;            // 0 Euler predictor, 1 AB3 predictor, 2 AM4 corrector
     int write_S;
@@ -198,39 +202,39 @@ __device__ __forceinline__ void stencil_body(const StencilArgs &A, int bx, int b
             const float qm = shr1(q1, hq0), qp = shl1(q1, hq0);
             F3 lox, hix;
             reconstruct(em, e2, ep, pm, p1, pp, qm, q1, qp, Dw, De, th, lox, hix);
-            const F3 hil = {shr1(hix.e, hix.e), shr1(hix.n, hix.n), shr1(hix.t, hix.t)};
+            const F3 hil = {shr1z(hix.e), shr1z(hix.n), shr1z(hix.t)};
             float Hw0, Hw1, Hw2;  // west face: (mass, x-momentum, y-momentum)
             cu_flux(g, eps, Dw, hil, lox, Hw0, Hw1, Hw2);
-            const float He0 = shl1(Hw0, Hw0), He1 = shl1(Hw1, Hw1), He2 = shl1(Hw2, Hw2);
+            const float He0 = shl1z(Hw0), He1 = shl1z(Hw1), He2 = shl1z(Hw2);
 
             float E = -(He0 - Hw0) * rdx - (Hn0 - Hs0) * rdy;
-            float F = -(He1 - Hw1) * rdx - (Hn2 - Hs2) * rdy + g * (De - Dw) * rdx * e2;
-            float G = -(He2 - Hw2) * rdx - (Hn1 - Hs1) * rdy + g * (Dn - Ds) * rdy * e2;
+            float F = -(He1 - Hw1) * rdx - (Hn2 - Hs2) * rdy + A.gx * (De - Dw) * e2;
+            float G = -(He2 - Hw2) * rdx - (Hn1 - Hs1) * rdy + A.gy * (Dn - Ds) * e2;
             float Fs = 0.f, Gs = 0.f;
 
             const float dep = fmaxf(Dc, 0.f);
-            const float dxm = shr1(dep, dep), dxp = shl1(dep, dep);
+            const float dxm = shr1z(dep), dxp = shl1z(dep);
             const float dym = fmaxf(Dcm, 0.f), dyp = fmaxf(Dcp, 0.f);
-            const float ddx = (dxp - dxm) * 0.5f * rdx, ddy = (dyp - dym) * 0.5f * rdy;
+            const float ddx = (dxp - dxm) * A.hx, ddy = (dyp - dym) * A.hy;
 
             if (d.model == BSNQ) {
-                const float em2 = shr1(em, em), ep2 = shl1(ep, ep);
-                const float epp = shl1(e3, e3), epm = shl1(e1, e1);
-                const float emp = shr1(e3, e3), emm = shr1(e1, e1);
-                const float exx = (ep - 2.f * e2 + em) * rdx * rdx;
-                const float eyy = (e3 - 2.f * e2 + e1) * rdy * rdy;
-                const float exy = (epp - epm - emp + emm) * 0.25f * rdx * rdy;
-                const float exxx = (ep2 - 2.f * ep + 2.f * em - em2) * 0.5f * rdx * rdx * rdx;
-                const float eyyy = (e4 - 2.f * e3 + 2.f * e1 - e0) * 0.5f * rdy * rdy * rdy;
-                const float exyy = ((epp - 2.f * ep + epm) - (emp - 2.f * em + emm)) * 0.5f * rdx * rdy * rdy;
-                const float exxy = ((epp - 2.f * e3 + emp) - (epm - 2.f * e1 + emm)) * 0.5f * rdx * rdx * rdy;
-                const float gb = Bd * g * dep * dep;
+                const float em2 = shr1z(em), ep2 = shl1z(ep);
+                const float epp = shl1z(e3), epm = shl1z(e1);
+                const float emp = shr1z(e3), emm = shr1z(e1);
+                const float exx = (ep - 2.f * e2 + em) * A.sxx;
+                const float eyy = (e3 - 2.f * e2 + e1) * A.syy;
+                const float exy = (epp - epm - emp + emm) * A.cxy;
+                const float exxx = (ep2 - 2.f * ep + 2.f * em - em2) * A.cxxx;
+                const float eyyy = (e4 - 2.f * e3 + 2.f * e1 - e0) * A.cyyy;
+                const float exyy = ((epp - 2.f * ep + epm) - (emp - 2.f * em + emm)) * A.cxyy;
+                const float exxy = ((epp - 2.f * e3 + emp) - (epm - 2.f * e1 + emm)) * A.cxxy;
+                const float gb = A.Bg * dep * dep;
                 F += gb * (dep * (exxx + exyy) + ddx * (2.f * exx + eyy) + ddy * exy);
                 G += gb * (dep * (eyyy + exxy) + ddy * (2.f * eyy + exx) + ddx * exy);
-                const float Px = (pp - pm) * 0.5f * rdx, Py = (p2 - p0) * 0.5f * rdy;
-                const float Pxy = (shl1(p2, p2) - shl1(p0, p0) - shr1(p2, p2) + shr1(p0, p0)) * 0.25f * rdx * rdy;
-                const float Qx = (qp - qm) * 0.5f * rdx, Qy = (q2 - q0) * 0.5f * rdy;
-                const float Qxy = (shl1(q2, q2) - shl1(q0, q0) - shr1(q2, q2) + shr1(q0, q0)) * 0.25f * rdx * rdy;
+                const float Px = (pp - pm) * A.hx, Py = (p2 - p0) * A.hy;
+                const float Pxy = (shl1z(p2) - shl1z(p0) - shr1z(p2) + shr1z(p0)) * A.cxy;
+                const float Qx = (qp - qm) * A.hx, Qy = (q2 - q0) * A.hy;
+                const float Qxy = (shl1z(q2) - shl1z(q0) - shr1z(q2) + shr1z(q0)) * A.cxy;
                 Fs = dep * (ddx * Qy + ddy * Qx) * (1.f / 6.f) + B3 * dep * dep * Qxy;
                 Gs = dep * (ddy * Px + ddx * Py) * (1.f / 6.f) + B3 * dep * dep * Pxy;
             }
