@@ -236,9 +236,13 @@ ws_status ws_batch_status(ws_batch *b, int32_t slot, int64_t *step, double *t, i
  * equations held per thread versus threads per barrier).  solver: the
  * reduced systems by PCR (WS_SOLVE_PCR) or by the Thomas algorithm with one
  * lane per system (WS_SOLVE_THOMAS: linear work, no barriers, a dependent
- * chain per lane).  Rows and threads do not change results (bitwise); the
- * solver changes only the rounding of the reduced solve. */
-enum { WS_SOLVE_PCR = 0, WS_SOLVE_THOMAS = 1 };  /* reduced-system strategy */
+ * chain per lane) or by factors computed once per bathymetry and boundary
+ * set (WS_SOLVE_LU: the same Thomas arithmetic, two multiply-adds per unknown
+ * per pass, system-interleaved storage; refactored automatically after
+ * ws_set_boundary, terrain edits and ws_restore).  Rows and threads do not
+ * change results (bitwise); THOMAS and LU give the same bits; PCR rounds the
+ * reduced solve differently. */
+enum { WS_SOLVE_PCR = 0, WS_SOLVE_THOMAS = 1, WS_SOLVE_LU = 2 };  /* reduced-system strategy */
 typedef struct {
     int32_t stencil_rows;
     int32_t pcr_threads;

@@ -50,6 +50,8 @@ struct ws_domain {
     float *hist[3][5];             // [slot][E, F, G, F*, G*]
     float4 *redx, *redy;
     float *solx, *soly;
+    float *lux, *luy;              // static factors of the reduced systems (factored solve)
+    bool lu_valid;
     float *ghost[2];               // wave-maker ghosts at t^n, t^{n+1}
     int gl;                        // ghost positions per layer
     double *tab[4];                // wave tables
@@ -85,7 +87,7 @@ static int roundup(int x, int m) { return (x + m - 1) / m * m; }
 
 struct Layout {
     int nxp, nyp, pitch, zpitch, nu, nv, gl;
-    size_t field, corners, redx, redy, solx, soly, ghost, tabs, misc, vtab, total;
+    size_t field, corners, redx, redy, solx, soly, lux, luy, ghost, tabs, misc, vtab, total;
     int nvar;
 };
 
@@ -111,6 +113,8 @@ static Layout layout(const ws_grid *g) {
     L.redy = align256(sizeof(float4) * (size_t)L.nxp * L.nv);
     L.solx = align256(sizeof(float) * (size_t)L.nyp * L.nu);
     L.soly = align256(sizeof(float) * (size_t)L.nxp * L.nv);
+    L.lux = align256(3 * sizeof(float) * (size_t)L.nyp * L.nu);
+    L.luy = align256(3 * sizeof(float) * (size_t)L.nxp * L.nv);
     L.ghost = align256(sizeof(float) * 4 * 2 * 3 * (size_t)L.gl);
     L.tabs = align256(sizeof(double) * MAXC * TABW);
     L.misc = 256;
@@ -118,7 +122,7 @@ static Layout layout(const ws_grid *g) {
     // (state buffer x step mod 3) and 9 x (n_corr + 1) passes of full steps
     L.nvar = 9 * (g->n_corr + 2);
     L.vtab = align256(L.nvar * (sizeof(StencilArgs) + sizeof(SolveArgs)));
-    L.total = 29 * L.field + 2 * L.corners + L.redx + L.redy + L.solx + L.soly + 2 * L.ghost +
+    L.total = 29 * L.field + 2 * L.corners + L.redx + L.redy + L.solx + L.soly + L.lux + L.luy + 2 * L.ghost +
               4 * L.tabs + L.misc + L.vtab;
     return L;
 }
@@ -358,6 +362,9 @@ extern "C" ws_status ws_domain_init(const ws_grid *g, const float *z_corners_dev
     d->redy = (float4 *)take(L.redy);
     d->solx = (float *)take(L.solx);
     d->soly = (float *)take(L.soly);
+    d->lux = (float *)take(L.lux);
+    d->luy = (float *)take(L.luy);
+    d->lu_valid = false;
     d->ghost[0] = (float *)take(L.ghost);
     d->ghost[1] = (float *)take(L.ghost);
     for (int s = 0; s < 4; ++s) d->tab[s] = (double *)take(L.tabs);
@@ -497,6 +504,7 @@ extern "C" ws_status ws_set_boundary(ws_domain *d, int32_t side, const ws_bounda
     }
     HIPCHK(hipMemcpy(d->tab[side], tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
     d->side_ncomp[side] = nc;
+    d->lu_valid = false;  // boundary rows of the reduced systems change
     batch_touch(d);
     return WS_OK;
 }
@@ -573,6 +581,7 @@ extern "C" ws_status ws_restore(ws_domain *d, const void *src_dev, size_t bytes,
     d->cur = 0;
     d->step = h.step;
     d->t = h.t;
+    d->lu_valid = false;  // bathymetry restored
     batch_touch(d);
     return WS_OK;
 }
@@ -656,6 +665,7 @@ extern "C" ws_status ws_apply_edit(ws_domain *d, int32_t kind, double x0, double
     HIPCHK(hipStreamSynchronize(st));
     if (flag) return fail(WS_ENOTDD, "ws_apply_edit: terrain edit rejected (eq. 23 would lose diagonal dominance)");
     std::swap(d->D, d->Dnew);
+    d->lu_valid = false;
     batch_touch(d);
     m = make_dom(d);
     hipLaunchKernelGGL(k_edit_velocity, cells_grid(d->g.nx, d->g.ny), dim3(256), 0, st, m, d->Dnew, e, p, q);
@@ -786,6 +796,9 @@ static void pass_args(const ws_domain *d, const Dom &m, bool euler, int cur, int
     so.gh0 = d->ghost[0];
     so.gh1 = d->ghost[1];
     so.health = d->health;
+    so.lux = d->lux;
+    so.luy = d->luy;
+    so.layout = d->solver == WS_SOLVE_LU ? 1 : 0;
     so.sponge = p == K ? 1 : 0;
 }
 
@@ -795,9 +808,29 @@ static bool has_makers(const ws_domain *d) {
     return false;
 }
 
+static int solve_waves(const ws_domain *d) { return (d->g.ny + 63) / 64 + (d->g.nx + 63) / 64; }
+
+// Factors of the reduced systems for the factored solve, when stale: a
+// coefficient-mode reduction (contiguous equations; its right-hand sides and
+// eliminated values are scratch) and one factorization sweep per system.
+static ws_status ensure_factors(ws_domain *d, hipStream_t st) {
+    if (d->solver != WS_SOLVE_LU || d->lu_valid) return WS_OK;
+    StencilArgs sa;
+    SolveArgs so;
+    pass_args(d, make_dom(d), false, d->cur, 0, 0, sa, so);
+    so.layout = 0;
+    hipLaunchKernelGGL(k_reduce, tiles(d), dim3(NT), 0, st, so);
+    hipLaunchKernelGGL(k_lu_factor, dim3(solve_waves(d)), dim3(64), 0, st, so, d->lux, d->luy);
+    HIPCHK(hipGetLastError());
+    d->lu_valid = true;
+    return WS_OK;
+}
+
 // The reduced row and column systems, by the domain's strategy.
 static void launch_reduced(const ws_domain *d, hipStream_t st, const SolveArgs &so) {
-    if (d->solver == WS_SOLVE_THOMAS) {
+    if (d->solver == WS_SOLVE_LU) {
+        hipLaunchKernelGGL(k_lu_solve, dim3(solve_waves(d)), dim3(64), 0, st, so);
+    } else if (d->solver == WS_SOLVE_THOMAS) {
         const int waves = (d->g.ny + 63) / 64 + (d->g.nx + 63) / 64;
         hipLaunchKernelGGL(k_thomas, dim3(waves), dim3(64), 0, st, so);
     } else {
@@ -831,6 +864,10 @@ extern "C" ws_status ws_advance(ws_domain *d, int64_t nsteps, void *stream) {
     if (!d || nsteps < 0) return fail(WS_EINVAL, "ws_advance: bad argument");
     if (d->batch) return fail(WS_EBUSY, "ws_advance: domain is attached to a batch (use ws_batch_advance)");
     hipStream_t st = (hipStream_t)stream;
+    if (nsteps > 0) {
+        ws_status r = ensure_factors(d, st);
+        if (r != WS_OK) return r;
+    }
     const Dom m = make_dom(d);
     const bool makers = has_makers(d);
     for (int64_t n = 0; n < nsteps; ++n) {
@@ -989,6 +1026,10 @@ static ws_status batch_upload(ws_batch *b) {
     int maxK = 0, nred = 0;
     for (int k = 0; k < n; ++k) {
         ws_domain *d = b->slots[order[k]];
+        if (d->solver != b->solver) {  // the batch's solve strategy (and layout) applies
+            d->solver = b->solver;
+            d->vdirty = true;
+        }
         if (d->vdirty) {
             ws_status r = write_vtab(d);
             if (r != WS_OK) return r;
@@ -1003,7 +1044,7 @@ static ws_status batch_upload(ws_batch *b) {
         const BatchDesc &D = desc[k];
         pre[0][k + 1] = pre[0][k] + D.sgx * D.sgy;
         pre[1][k + 1] = pre[1][k] + D.tgx * D.tgy;
-        pre[2][k + 1] = pre[2][k] + (b->solver == WS_SOLVE_THOMAS ? (D.d.ny + 63) / 64 + (D.d.nx + 63) / 64 : D.nsys);
+        pre[2][k + 1] = pre[2][k] + (b->solver != WS_SOLVE_PCR ? (D.d.ny + 63) / 64 + (D.d.nx + 63) / 64 : D.nsys);
         pre[3][k + 1] = pre[3][k] + (D.makers ? (8 * D.d.gl + 255) / 256 : 0);
         maxK = D.K > maxK ? D.K : maxK;
         const int nr = d->nu > d->nv ? d->nu : d->nv;
@@ -1040,7 +1081,9 @@ static ws_status batch_step(ws_batch *b, hipStream_t st) {
 #undef L4
         hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NT), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, p);
         const size_t shm = sizeof(float4) * b->nred;
-        if (b->solver == WS_SOLVE_THOMAS)
+        if (b->solver == WS_SOLVE_LU)
+            hipLaunchKernelGGL(kb_lu_solve, pg, dim3(64), 0, st, b->d_desc, b->d_state, b->d_pre[2], n, p);
+        else if (b->solver == WS_SOLVE_THOMAS)
             hipLaunchKernelGGL(kb_thomas, pg, dim3(64), 0, st, b->d_desc, b->d_state, b->d_pre[2], n, p);
         else
             pcr_dispatch(b->pnt, pcr_epl(b->pnt, b->nred), [&](auto shape) {
@@ -1152,6 +1195,10 @@ extern "C" ws_status ws_batch_advance(ws_batch *b, int64_t nsteps, void *stream)
         if (r != WS_OK) return r;
     }
     if (b->order.empty() || nsteps == 0) return WS_OK;
+    for (int sl : b->order) {
+        ws_status r = ensure_factors(b->slots[sl], st);
+        if (r != WS_OK) return r;
+    }
     b->last = st;
     if (st != nullptr && (!b->exec || b->gstream != st)) {
         batch_drop_graph(b);
@@ -1190,7 +1237,7 @@ static bool tuning_ok(const ws_tuning *t) {
     return t && (t->stencil_rows == 8 || t->stencil_rows == 16 || t->stencil_rows == 24 ||
                  t->stencil_rows == 32 || t->stencil_rows == 48 || t->stencil_rows == 64) &&
            (t->pcr_threads == 64 || t->pcr_threads == 128 || t->pcr_threads == 256) &&
-           (t->solver == WS_SOLVE_PCR || t->solver == WS_SOLVE_THOMAS);
+           (t->solver == WS_SOLVE_PCR || t->solver == WS_SOLVE_THOMAS || t->solver == WS_SOLVE_LU);
 }
 
 extern "C" ws_status ws_get_tuning(const ws_domain *d, ws_tuning *out) {
@@ -1206,6 +1253,7 @@ extern "C" ws_status ws_set_tuning(ws_domain *d, const ws_tuning *t) {
     if (!d || !tuning_ok(t)) return fail(WS_EINVAL, "ws_set_tuning: bad tuning");
     d->sy = t->stencil_rows;
     d->pnt = t->pcr_threads;
+    if (d->solver != t->solver) batch_touch(d);  // argument blocks carry the solve layout
     d->solver = t->solver;
     return WS_OK;
 }
@@ -1293,6 +1341,7 @@ extern "C" ws_status ws_tune(ws_domain *d, const char *cache_path, void *stream,
     for (int c = 0; c < 6; ++c)
         if (t_rows[c] < best_s) { best_s = t_rows[c]; best.stencil_rows = rows[c]; }
     // the reduced systems need valid equations: one reduction of the increments
+    so.layout = 0;
     hipLaunchKernelGGL(k_reduce, tiles(d), dim3(NT), 0, st, so);
     const int nred = d->nu > d->nv ? d->nu : d->nv;
     const int threads[3] = {64, 128, 256};
@@ -1322,6 +1371,32 @@ extern "C" ws_status ws_tune(ws_domain *d, const char *cache_path, void *stream,
             total += ms;
         }
         if (total < best_p) { best_p = total; best.solver = WS_SOLVE_THOMAS; }
+    }
+    {
+        // factored solve: factors once (kept: they match the domain's current
+        // bathymetry and boundaries), then only the right-hand-side sweeps
+        const int keep = d->solver;
+        d->solver = WS_SOLVE_LU;
+        ws_status r = ensure_factors(d, st);
+        if (r != WS_OK) {
+            d->solver = keep;
+            return r;
+        }
+        SolveArgs s1 = so;
+        s1.layout = 1;
+        float total = 0.f;
+        for (int k = 0; k < reps; ++k) {
+            hipLaunchKernelGGL(k_reduce, tiles(d), dim3(NT), 0, st, s1);
+            HIPCHK(hipEventRecord(e0, st));
+            hipLaunchKernelGGL(k_lu_solve, dim3(solve_waves(d)), dim3(64), 0, st, s1);
+            HIPCHK(hipEventRecord(e1, st));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            total += ms;
+        }
+        d->solver = keep;
+        if (total < best_p) { best_p = total; best.solver = WS_SOLVE_LU; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1414,6 +1489,25 @@ extern "C" ws_status ws_batch_tune(ws_batch *b, void *stream, ws_tuning *out) {
             if (k > 0) total += ms;
         }
         best_solver = total < best ? WS_SOLVE_THOMAS : WS_SOLVE_PCR;
+        if (total < best) best = total;
+        // factored solve: argument blocks with the interleaved layout, factors
+        b->solver = WS_SOLVE_LU;  // trial
+        b->dirty = true;
+        if ((r = batch_upload(b)) != WS_OK) return r;
+        for (int sl : b->order)
+            if ((r = ensure_factors(b->slots[sl], st)) != WS_OK) return r;
+        total = 0.f;
+        for (int k = 0; k < 4; ++k) {
+            hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NT), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, 1);
+            (void)hipEventRecord(e0, st);
+            hipLaunchKernelGGL(kb_lu_solve, dim3(b->total[2]), dim3(64), 0, st, b->d_desc, b->d_state, b->d_pre[2], n, 1);
+            (void)hipEventRecord(e1, st);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (k > 0) total += ms;
+        }
+        if (total < best) best_solver = WS_SOLVE_LU;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -300,6 +300,13 @@ struct SolveArgs {
     float *rx, *ry;            // right-hand sides in, eliminated segment interiors out
     float4 *redx, *redy;       // reduced equations (sub, diag, super, rhs) per unknown
     float *solx, *soly;        // reduced solutions
+    // layout 1 (factored solve): the reduced right-hand sides (in the memory of
+    // redx, redy) and the solutions are system-interleaved, unknown k of row
+    // system j at k * ny + j (columns: k * nx + i); lux, luy hold the static
+    // factors, likewise interleaved: (a, 1/pivot) pairs, then the modified
+    // super-diagonals.
+    const float *lux, *luy;
+    int layout;
     float *eta, *pout, *qout;  // new surface (read; sponge writes it), new P, Q
     const float *pbase, *qbase;  // P^n, Q^n of the step
     const float *gh0, *gh1;    // wave-maker ghosts at t^n and t^{n+1}
@@ -467,9 +474,18 @@ __device__ __forceinline__ void reduce_body(const SolveArgs &A, SolveTile &s, in
         float *r = &s.rx[row][k0];
         seg_coefs<MX>(A, s, i0, j0, 0, k0, row, a, b, c, r, 1);
         seg_eliminate<MX>(r, 1, a, b, c, first, last);
-        float4 *red = A.redx + (size_t)(j0 + row) * d.nu + 2 * (bx * (TX / MX) + seg);
-        red[0] = first;
-        red[1] = last;
+        const int k = 2 * (bx * (TX / MX) + seg), j = j0 + row;
+        if (A.layout) {
+            if (j < d.ny) {
+                float *rr = reinterpret_cast<float *>(A.redx);
+                rr[(size_t)k * d.ny + j] = first.w;
+                rr[(size_t)(k + 1) * d.ny + j] = last.w;
+            }
+        } else {
+            float4 *red = A.redx + (size_t)j * d.nu + k;
+            red[0] = first;
+            red[1] = last;
+        }
     } else if (tid < 128) {
         const int col = tid - 64;
         float a[TY], b[TY], c[TY];
@@ -477,9 +493,18 @@ __device__ __forceinline__ void reduce_body(const SolveArgs &A, SolveTile &s, in
         float *r = &s.ry[0][col];
         seg_coefs<TY>(A, s, i0, j0, 1, col, 0, a, b, c, r, TXP);
         seg_eliminate<TY>(r, TXP, a, b, c, first, last);
-        float4 *red = A.redy + (size_t)(i0 + col) * d.nv + 2 * by;
-        red[0] = first;
-        red[1] = last;
+        const int i = i0 + col;
+        if (A.layout) {
+            if (i < d.nx) {
+                float *rr = reinterpret_cast<float *>(A.redy);
+                rr[(size_t)(2 * by) * d.nx + i] = first.w;
+                rr[(size_t)(2 * by + 1) * d.nx + i] = last.w;
+            }
+        } else {
+            float4 *red = A.redy + (size_t)i * d.nv + 2 * by;
+            red[0] = first;
+            red[1] = last;
+        }
     }
     __syncthreads();
     for (int k = tid; k < TX * TY; k += NT) {
@@ -490,7 +515,7 @@ __device__ __forceinline__ void reduce_body(const SolveArgs &A, SolveTile &s, in
     }
 }
 
-__global__ __launch_bounds__(NT) void k_reduce(SolveArgs A) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_reduce(SolveArgs A) {
     __shared__ SolveTile s;
     reduce_body(A, s, blockIdx.x, blockIdx.y);
 }
@@ -535,6 +560,118 @@ __device__ __forceinline__ void thomas_body(const SolveArgs &A, int wave, int la
 }
 
 __global__ __launch_bounds__(64) void k_thomas(SolveArgs A) { thomas_body(A, blockIdx.x, threadIdx.x); }
+
+// Factored solve of the reduced systems.  Their matrices depend only on the
+// depth and the boundary types, so they are factored once (Thomas
+// elimination, k_lu_factor, from the equations a coefficient-mode reduction
+// writes) and every pass only sweeps the right-hand side forward and back:
+// two fused multiply-adds per unknown, one lane per system, all accesses
+// system-interleaved so that a wave's 64 lanes read 256 contiguous bytes.
+// The arithmetic is the lane-per-system Thomas solve's, so both give the same
+// bits.
+__device__ __forceinline__ void lu_factor_lane(int N, const float4 *eq, float2 *fai, float *fcp, size_t stride) {
+    float cp = 0.f;
+    for (int k = 0; k < N; ++k) {
+        const float4 e = eq[k];
+        const float inv = frcp(e.y - e.x * cp);
+        cp = e.z * inv;
+        fai[k * stride] = make_float2(e.x, inv);
+        fcp[k * stride] = cp;
+    }
+}
+
+// The sweeps go in blocks whose loads are all issued before the block's
+// dependent chain: the chain is a few cycles per unknown, a load about a
+// microsecond, so a block's loads share one latency.  A block is as long as
+// the outstanding-load counter allows (two loads per unknown, 63 in flight).
+constexpr int LU_U = 30;
+__device__ __forceinline__ void lu_solve_lane(int N, const float *r, const float2 *fai, const float *fcp, float *x,
+                                              size_t stride) {
+    float dp = 0.f;
+    int k = 0;
+    for (; k + LU_U <= N; k += LU_U) {
+        float rr[LU_U];
+        float2 ai[LU_U];
+#pragma unroll
+        for (int u = 0; u < LU_U; ++u) {
+            const size_t o = (size_t)(k + u) * stride;
+            rr[u] = r[o];
+            ai[u] = fai[o];
+        }
+#pragma unroll
+        for (int u = 0; u < LU_U; ++u) {
+            dp = (rr[u] - ai[u].x * dp) * ai[u].y;
+            x[(size_t)(k + u) * stride] = dp;
+        }
+    }
+    for (; k < N; ++k) {
+        const size_t o = (size_t)k * stride;
+        const float2 ai = fai[o];
+        dp = (r[o] - ai.x * dp) * ai.y;
+        x[o] = dp;
+    }
+    float v = dp;
+    k = N - 2;
+    for (; k - LU_U + 1 >= 0; k -= LU_U) {
+        float xx[LU_U], cc[LU_U];
+#pragma unroll
+        for (int u = 0; u < LU_U; ++u) {
+            const size_t o = (size_t)(k - u) * stride;
+            xx[u] = x[o];
+            cc[u] = fcp[o];
+        }
+#pragma unroll
+        for (int u = 0; u < LU_U; ++u) {
+            v = xx[u] - cc[u] * v;
+            x[(size_t)(k - u) * stride] = v;
+        }
+    }
+    for (; k >= 0; --k) {
+        const size_t o = (size_t)k * stride;
+        v = x[o] - fcp[o] * v;
+        x[o] = v;
+    }
+}
+
+// Waves 0 .. xw-1 take the row systems, the rest the column systems.
+__device__ __forceinline__ void lu_factor_body(const SolveArgs &A, float *lux, float *luy, int wave, int lane) {
+    const Dom &d = A.d;
+    const int xw = (d.ny + 63) / 64;
+    if (wave < xw) {
+        const int j = wave * 64 + lane;
+        const size_t n = (size_t)d.nu * d.ny;
+        if (j < d.ny)
+            lu_factor_lane(d.nu, A.redx + (size_t)j * d.nu, reinterpret_cast<float2 *>(lux) + j, lux + 2 * n + j, d.ny);
+    } else {
+        const int i = (wave - xw) * 64 + lane;
+        const size_t n = (size_t)d.nv * d.nx;
+        if (i < d.nx)
+            lu_factor_lane(d.nv, A.redy + (size_t)i * d.nv, reinterpret_cast<float2 *>(luy) + i, luy + 2 * n + i, d.nx);
+    }
+}
+
+__device__ __forceinline__ void lu_solve_body(const SolveArgs &A, int wave, int lane) {
+    const Dom &d = A.d;
+    const int xw = (d.ny + 63) / 64;
+    if (wave < xw) {
+        const int j = wave * 64 + lane;
+        const size_t n = (size_t)d.nu * d.ny;
+        if (j < d.ny)
+            lu_solve_lane(d.nu, reinterpret_cast<const float *>(A.redx) + j, reinterpret_cast<const float2 *>(A.lux) + j,
+                          A.lux + 2 * n + j, A.solx + j, d.ny);
+    } else {
+        const int i = (wave - xw) * 64 + lane;
+        const size_t n = (size_t)d.nv * d.nx;
+        if (i < d.nx)
+            lu_solve_lane(d.nv, reinterpret_cast<const float *>(A.redy) + i, reinterpret_cast<const float2 *>(A.luy) + i,
+                          A.luy + 2 * n + i, A.soly + i, d.nx);
+    }
+}
+
+__global__ __launch_bounds__(64) void k_lu_factor(SolveArgs A, float *lux, float *luy) {
+    lu_factor_body(A, lux, luy, blockIdx.x, threadIdx.x);
+}
+__global__ __launch_bounds__(64) void k_lu_solve(SolveArgs A) { lu_solve_body(A, blockIdx.x, threadIdx.x); }
 
 // Parallel cyclic reduction of one reduced system (rows first, then
 // columns): each thread keeps its equations (k = tid + j * PCR_NT) in
@@ -619,16 +756,38 @@ __device__ __forceinline__ void expand_body(const SolveArgs &A, SolveTile &s, in
     }
     if (tid < 64) {
         const int row = tid % 16, seg = tid / 16, k0 = seg * MX;
-        const float *sol = A.solx + (size_t)(j0 + row) * d.nu + 2 * (bx * (TX / MX) + seg);
+        const int k = 2 * (bx * (TX / MX) + seg), j = j0 + row;
+        float x0 = 0.f, xl = 0.f;
+        if (A.layout) {
+            if (j < d.ny) {
+                x0 = A.solx[(size_t)k * d.ny + j];
+                xl = A.solx[(size_t)(k + 1) * d.ny + j];
+            }
+        } else {
+            const float *sol = A.solx + (size_t)j * d.nu + k;
+            x0 = sol[0];
+            xl = sol[1];
+        }
         float a[MX], b[MX], c[MX];
         seg_coefs<MX>(A, s, i0, j0, 0, k0, row, a, b, c, nullptr, 1);
-        seg_expand<MX>(&s.rx[row][k0], 1, a, b, c, sol[0], sol[1]);
+        seg_expand<MX>(&s.rx[row][k0], 1, a, b, c, x0, xl);
     } else if (tid < 128) {
         const int col = tid - 64;
-        const float *sol = A.soly + (size_t)(i0 + col) * d.nv + 2 * by;
+        const int i = i0 + col;
+        float x0 = 0.f, xl = 0.f;
+        if (A.layout) {
+            if (i < d.nx) {
+                x0 = A.soly[(size_t)(2 * by) * d.nx + i];
+                xl = A.soly[(size_t)(2 * by + 1) * d.nx + i];
+            }
+        } else {
+            const float *sol = A.soly + (size_t)i * d.nv + 2 * by;
+            x0 = sol[0];
+            xl = sol[1];
+        }
         float a[TY], b[TY], c[TY];
         seg_coefs<TY>(A, s, i0, j0, 1, col, 0, a, b, c, nullptr, TXP);
-        seg_expand<TY>(&s.ry[0][col], TXP, a, b, c, sol[0], sol[1]);
+        seg_expand<TY>(&s.ry[0][col], TXP, a, b, c, x0, xl);
     }
     __syncthreads();
     int bad = 0;

@@ -241,12 +241,29 @@ def test_tunings_identical_results_and_autotuner(tmp_path):
     th.advance(30)
     for x, y in zip(ref.state_numpy(), th.state_numpy()):
         assert np.abs(x - y).max() <= 1e-6 * max(1.0, np.abs(x).max())
+    # the factored solve repeats the Thomas arithmetic with stored factors:
+    # the same bits, also across a terrain edit and a boundary change (both
+    # refactor) and a restore
+    lu = make(w)
+    lu.set_tuning(8, 128, ws.SOLVE_LU)
+    lu.advance(30)
+    same(th, lu, "factored solve vs Thomas")
+    snap = lu.snapshot()
+    for dd in (th, lu):
+        assert dd.apply_edit(ws.EDIT_TERRAIN, 0.7 * w.nx * w.dx, 0.6 * w.ny * w.dy, 0.15, 6 * w.dx) == 0
+        dd.set_boundary(ws.EAST, ws.SPONGE, 12)
+        dd.advance(15)
+    same(th, lu, "factored solve after edit and boundary change")
+    for dd in (th, lu):
+        dd.restore(snap)
+        dd.advance(5)
+    same(th, lu, "factored solve after restore")
     d = make(w)
     d.advance(30)
     before = d.state_numpy()
     cache = str(tmp_path / "tune.txt")
     t = d.tune(cache)
-    assert t[0] in (8, 16, 24, 32, 48, 64) and t[1] in (64, 128, 256) and t[2] in (0, 1)
+    assert t[0] in (8, 16, 24, 32, 48, 64) and t[1] in (64, 128, 256) and t[2] in (0, 1, 2)
     assert d.tuning() == t
     after = d.state_numpy()
     assert all(np.array_equal(x, y) for x, y in zip(before, after)) and d.query()[0] == 30
@@ -266,7 +283,7 @@ def test_tunings_identical_results_and_autotuner(tmp_path):
     B.attach(b)
     B.advance(20)
     tb = B.tune()                                  # leaves the states alone
-    assert tb[0] in (8, 16, 24, 32, 48, 64) and tb[1] in (64, 128, 256) and tb[2] in (0, 1)
+    assert tb[0] in (8, 16, 24, 32, 48, 64) and tb[1] in (64, 128, 256) and tb[2] in (0, 1, 2)
     B.set_tuning(tb[0], tb[1], ws.SOLVE_PCR)
     B.advance(20)
     B.sync()
@@ -281,4 +298,13 @@ def test_tunings_identical_results_and_autotuner(tmp_path):
     th2.advance(30)
     B.sync()
     same(th2, th2b, "batched Thomas")
+    lu2 = make(w)                                  # batched factored solve equals single-domain
+    lu2b = make(w)
+    lu2.set_tuning(16, 128, ws.SOLVE_LU)
+    B.set_tuning(16, 128, ws.SOLVE_LU)
+    B.attach(lu2b)
+    B.advance(25)
+    lu2.advance(25)
+    B.sync()
+    same(lu2, lu2b, "batched factored solve")
     B.close()
