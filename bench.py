@@ -146,7 +146,8 @@ def batched_vs_plain(args, torch, ws, wl):
             "batched_over_plain_graph": (cells * n / t_b) / (cells * 3 * reps / t_g),
             "batched_over_plain_eager": (cells * n / t_b) / (cells * n / t_p),
             "unit": "cell-updates/s", "healthy": all(h == 0 for h in health),
-            "batch_tuning": {"stencil_rows": tuning[0], "pcr_threads": tuning[1]}}
+            "batch_tuning": {"stencil_rows": tuning[0], "pcr_threads": tuning[1],
+                             "solver": ("pcr", "thomas", "lu")[tuning[2]]}}
 
 
 def serving(args):
@@ -276,7 +277,8 @@ def main():
         "data": "synthetic (seeded shelf bathymetry + fractal noise, JONSWAP maker)",
         "config": {"workload": w.name + "_jonswap64_sponge64", "nx": w.nx, "ny": w.ny,
                    "dx_m": w.dx, "dt_s": w.dt, "n_corr": 2, "fstar_extrap": 1,
-                   "tuning": {"stencil_rows": tuning[0], "pcr_threads": tuning[1]},
+                   "tuning": {"stencil_rows": tuning[0], "pcr_threads": tuning[1],
+                              "solver": ("pcr", "thomas", "lu")[tuning[2]]},
                    "boundaries": "W waves(64 comps) / E sponge(64) / N,S walls"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
