@@ -691,7 +691,9 @@ static dim3 strips(const ws_domain *d) { return strips_for(d, d->sy); }
     } while (0)
 
 static void launch_stencil(int sy, dim3 grid, hipStream_t st, const StencilArgs &sa) {
-#define L3(KERN) hipLaunchKernelGGL(KERN, grid, dim3(64 * SWG), 0, st, sa)
+    const dim3 g1(grid.x * grid.y);  // 1-D grid in XCD-aware tile order
+    const int gx = (int)grid.x;
+#define L3(KERN) hipLaunchKernelGGL(KERN, g1, dim3(64 * SWG), 0, st, sa, gx)
     SY_SWITCH(k_stencil, sy, L3);
 #undef L3
 }

@@ -85,7 +85,8 @@ template <int SYT>
 __global__ __launch_bounds__(64 * SWG) __attribute__((amdgpu_waves_per_eu(4))) void kb_stencil(const BatchDesc *__restrict__ descs,
                                                        const BatchState *__restrict__ states,
                                                        const int *__restrict__ prefix, int ndom, int p) {
-    const int b = blockIdx.x, dm = find_dom(prefix, ndom, b);
+    // XCD-aware order over all strips of all domains (as in k_stencil)
+    const int b = xcd_order(blockIdx.x, gridDim.x), dm = find_dom(prefix, ndom, b);
     const BatchDesc &D = descs[dm];
     const int v = variant(D, states[dm], p);
     if (v < 0) return;

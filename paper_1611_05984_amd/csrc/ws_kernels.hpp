@@ -291,8 +291,27 @@ __device__ __forceinline__ void stencil_body(const StencilArgs &A, int bx, int b
     }
 }
 
+// XCD-aware order of a 1-D grid of G workgroups over a gx x gy tile grid.
+// Workgroups go round-robin to the 8 XCDs (b mod 8), each with its own L2;
+// XCD x gets a contiguous band of tiles in row-major order, so the strips
+// it runs side by side include vertical neighbours, whose halo rows it
+// reads through its own L2, while rows stay contiguous in memory.
+__device__ __forceinline__ int xcd_order(int b, int G) {
+    const int q = G >> 3, rem = G & 7, x = b & 7, i = b >> 3;
+    return x * q + (x < rem ? x : rem) + i;
+}
+__device__ __forceinline__ void xcd_tile(int b, int G, int gx, int &bx, int &by) {
+    const int t = xcd_order(b, G);
+    by = t / gx;
+    bx = t - by * gx;
+}
+
 template <int SYT>
-__global__ __launch_bounds__(64 * SWG) __attribute__((amdgpu_waves_per_eu(4))) void k_stencil(StencilArgs A) { stencil_body<SYT>(A, blockIdx.x, blockIdx.y); }
+__global__ __launch_bounds__(64 * SWG) __attribute__((amdgpu_waves_per_eu(4))) void k_stencil(StencilArgs A, int gx) {
+    int bx, by;
+    xcd_tile(blockIdx.x, gridDim.x, gx, bx, by);
+    stencil_body<SYT>(A, bx, by);
+}
 
 // ------------------------------------------------------------- solver parts
 struct SolveArgs {
