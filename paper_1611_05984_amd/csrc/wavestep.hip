@@ -878,7 +878,7 @@ extern "C" ws_status ws_advance(ws_domain *d, int64_t nsteps, void *stream) {
         const int K = euler ? 0 : d->g.n_corr;
         const double t0 = d->t, t1 = d->t + d->g.dt;
         if (makers) {
-            const int n = 8 * d->gl;
+            const int n = 8 * d->gl * GHL;
             hipLaunchKernelGGL(k_ghosts, dim3((n + 255) / 256), dim3(256), 0, st, m, d->ghost[0], t0);
             hipLaunchKernelGGL(k_ghosts, dim3((n + 255) / 256), dim3(256), 0, st, m, d->ghost[1], t1);
         }
@@ -1047,7 +1047,7 @@ static ws_status batch_upload(ws_batch *b) {
         pre[0][k + 1] = pre[0][k] + D.sgx * D.sgy;
         pre[1][k + 1] = pre[1][k] + D.tgx * D.tgy;
         pre[2][k + 1] = pre[2][k] + (b->solver != WS_SOLVE_PCR ? (D.d.ny + 63) / 64 + (D.d.nx + 63) / 64 : D.nsys);
-        pre[3][k + 1] = pre[3][k] + (D.makers ? (8 * D.d.gl + 255) / 256 : 0);
+        pre[3][k + 1] = pre[3][k] + (D.makers ? (8 * D.d.gl * GHL + 255) / 256 : 0);
         maxK = D.K > maxK ? D.K : maxK;
         const int nr = d->nu > d->nv ? d->nu : d->nv;
         nred = nr > nred ? nr : nred;

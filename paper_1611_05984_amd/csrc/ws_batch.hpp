@@ -176,14 +176,14 @@ __global__ __launch_bounds__(64) void kb_lu_solve(const BatchDesc *__restrict__ 
 }
 
 // Wave-maker ghosts of t^n (which = 0) and t^{n+1} (which = 1); 256 threads
-// per block, 8 gl threads per domain with wave makers.
+// per block, 8 gl GHL threads per domain with wave makers.
 __global__ void kb_ghosts(const BatchDesc *descs, const BatchState *states, const int *prefix, int ndom,
                           int which) {
     const int b = blockIdx.x, dm = find_dom(prefix, ndom, b);
     const BatchDesc &D = descs[dm];
     if (!D.makers || paused(states[dm])) return;
     const int k = (b - prefix[dm]) * blockDim.x + threadIdx.x;
-    if (k >= 8 * D.d.gl) return;
+    if (k >= 8 * D.d.gl * GHL) return;  // whole lane groups (8 gl GHL is a multiple of GHL)
     const double t = states[dm].t + (which ? D.dt : 0.0);
     ghosts_body(D.d, D.ghost[which], t, k);
 }

@@ -74,6 +74,20 @@ __device__ __forceinline__ float corner_D(const Dom &d, int ci, int cj) {
 // Wave-maker values at (x, y, t): sum of a sin(omega t + phi - kx x - ky y),
 // discharges c cos(theta) eta, c sin(theta) eta per component.  The phase is
 // formed and reduced to [-pi, pi] in double, the sine taken in single.
+// Components first, first + stride, ... of the sum (one lane's share).
+__device__ inline void wave_partial(const SideDev &s, double x, double y, double t, int first, int stride,
+                                    float &se, float &sp, float &sq) {
+    for (int m = first; m < s.ncomp; m += stride) {
+        const double *c = s.tab + TABW * m;
+        double ph = c[1] * t + c[6] - (c[2] * x + c[3] * y);
+        ph -= 6.283185307179586 * rint(ph * 0.15915494309189535);
+        const float v = (float)c[0] * sinf((float)ph);
+        se += v;
+        sp += (float)c[4] * v;
+        sq += (float)c[5] * v;
+    }
+}
+
 __device__ inline void wave_eval(const SideDev &s, double x, double y, double t, float &e,
                                  float &p, float &q) {
     float se = 0.f, sp = 0.f, sq = 0.f;

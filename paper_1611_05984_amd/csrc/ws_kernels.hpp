@@ -54,23 +54,40 @@ __device__ __forceinline__ float dcell4(float a, float b, float c, float d) {
 }
 
 // Ghost values of every wave-maker side at time t (eqs. 25-28 per component).
+// GHL lanes share one ghost cell, each summing every GHL-th component; the
+// partial sums meet by butterfly shuffles, so a 64-component maker keeps
+// the whole chip busy instead of one lane per cell.  Thread k: cell k / GHL.
+constexpr int GHL = 16;
 __device__ __forceinline__ void ghosts_body(const Dom &d, float *gh, double t, int k) {
-    const int pos = k % d.gl, layer = (k / d.gl) % 2, side = k / (2 * d.gl);
-    if (side >= 4 || d.side[side].type != BC_WAVES) return;
-    int i, j;
-    if (side < 2) {
-        i = side == 0 ? -1 - layer : d.nx + layer;
-        j = pos - 2;
-    } else {
-        j = side == 2 ? -1 - layer : d.ny + layer;
-        i = pos - 2;
+    const int cell = k / GHL, sub = k % GHL;
+    const int pos = cell % d.gl, layer = (cell / d.gl) % 2, side = cell / (2 * d.gl);
+    // lanes of one cell are consecutive and stay together through the shuffles
+    const bool live = side < 4 && d.side[side < 4 ? side : 0].type == BC_WAVES;
+    float se = 0.f, sp = 0.f, sq = 0.f;
+    if (live) {
+        const SideDev &sd = d.side[side];
+        int i, j;
+        if (side < 2) {
+            i = side == 0 ? -1 - layer : d.nx + layer;
+            j = pos - 2;
+        } else {
+            j = side == 2 ? -1 - layer : d.ny + layer;
+            i = pos - 2;
+        }
+        wave_partial(sd, (i + 0.5) * (double)d.dx, (j + 0.5) * (double)d.dy, t, sub, GHL, se, sp, sq);
     }
-    float e, p, q;
-    wave_eval(d.side[side], (i + 0.5) * (double)d.dx, (j + 0.5) * (double)d.dy, t, e, p, q);
-    float *o = gh + ghost_index(d, side, layer, pos);
-    o[0] = e;
-    o[1] = p;
-    o[2] = q;
+#pragma unroll
+    for (int m = GHL / 2; m >= 1; m >>= 1) {
+        se += __shfl_xor(se, m, GHL);
+        sp += __shfl_xor(sp, m, GHL);
+        sq += __shfl_xor(sq, m, GHL);
+    }
+    if (live && sub == 0) {
+        float *o = gh + ghost_index(d, side, layer, pos);
+        o[0] = se;
+        o[1] = sp;
+        o[2] = sq;
+    }
 }
 
 __global__ void k_ghosts(Dom d, float *gh, double t) { ghosts_body(d, gh, t, blockIdx.x * blockDim.x + threadIdx.x); }
