@@ -29,17 +29,26 @@ TUNING_CACHE = os.path.join(ROOT, "paper_1611_05984_amd", "tuning_cache.txt")
 #              history n-2 (E, F, G); writes history n (5), corrector bases (3),
 #              eta, dU*, dV*                                 -> 12 + 11 = 23
 #   corrector: reads eta, P, Q, depth, bases (3); writes eta, dU*, dV* -> 7 + 3 = 10
-#   reduce:    reads dU*, dV*, depth; writes the eliminated values and the
-#              reduced equations (two 4-word equations per 16-cell row segment
-#              and per 16-cell column segment)             -> 3 + 2 + 1 = 6
-#   pcr:       reads the reduced equations, writes their solutions -> 1 + 0.25
+#   reduce:    reads dU*, dV*, depth; writes the eliminated values and, per
+#              16-cell row segment and 16-cell column segment, two reduced
+#              equations (4 words each; PCR and lane Thomas) or two right-hand
+#              sides (factored solve)                       -> 3 + 2 + 1 or 0.25
+#   reduced solve: PCR reads the equations, writes the solutions: 1 + 0.25;
+#              lane Thomas also writes and rereads its sweep values: 1 + 0.5 +
+#              0.5 + 0.25; factored solve reads the right-hand sides and three
+#              factors, writes the solutions: 0.25 + 0.75 + 0.25
 #   expand:    reads eliminated values (2), P^n, Q^n, eta, depth, end values;
 #              writes P, Q                                  -> 6.25 + 2
-ALG_WORDS = {"k_stencil[predictor]": 23.0, "k_stencil[corrector]": 10.0,
-             "k_reduce": 6.0, "k_pcr": 1.25, "k_expand": 8.25}
+def alg_words(solver):
+    reduce_w = 5.25 if solver == 2 else 6.0
+    solve_w = {0: 1.25, 1: 2.25, 2: 1.25}[solver]
+    return {"k_stencil[predictor]": 23.0, "k_stencil[corrector]": 10.0,
+            "k_reduce": reduce_w, "reduced_solve": solve_w, "k_expand": 8.25}
+
+
 # kernel function -> its launch classes
 FUNCS = {"k_stencil": ("k_stencil[predictor]", "k_stencil[corrector]"), "k_reduce": ("k_reduce",),
-         "k_pcr": ("k_pcr",), "k_expand": ("k_expand",)}
+         "reduced_solve": ("reduced_solve",), "k_expand": ("k_expand",)}
 
 
 def parse():
@@ -240,17 +249,19 @@ def main():
     prof = D.profile_collect()
     D.profile(False)
     tot = sum(ms for ms, n in prof.values())
+    ALG_WORDS = alg_words(tuning[2])
     fsum = {f: (sum(prof[c][0] for c in cs), sum(prof[c][1] for c in cs),
                 sum(ALG_WORDS[c] * prof[c][1] for c in cs)) for f, cs in FUNCS.items()}
     dom_func = max(fsum, key=lambda f: fsum[f][0])
     # kernel symbol as the profiler names it (template instance of the tuned shape)
-    dom_name = {"k_stencil": "k_stencil<%d>" % tuning[0]}.get(dom_func, dom_func)
+    dom_name = {"k_stencil": "k_stencil<%d>" % tuning[0],
+                "reduced_solve": ("k_pcr", "k_thomas", "k_lu_solve")[tuning[2]]}.get(dom_func, dom_func)
     dom_ms, dom_n, dom_words = fsum[dom_func]
     avg_s = dom_ms / dom_n / 1e3
     alg_bytes = dom_words / dom_n * 4.0 * cells
     achieved = alg_bytes / avg_s / 1e9
     step_words = (ALG_WORDS["k_stencil[predictor]"] + 2 * ALG_WORDS["k_stencil[corrector]"] +
-                  3 * (ALG_WORDS["k_reduce"] + ALG_WORDS["k_pcr"] + ALG_WORDS["k_expand"]))
+                  3 * (ALG_WORDS["k_reduce"] + ALG_WORDS["reduced_solve"] + ALG_WORDS["k_expand"]))
     kernels = {k: {"ms_avg": (ms / n if n else 0.0), "launches": n,
                    "share": (ms / tot if tot else 0.0),
                    "alg_GBs": (ALG_WORDS[k] * 4 * cells / (ms / n / 1e3) / 1e9 if n else 0.0)}
@@ -312,7 +323,7 @@ def main():
 def _source_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("ws_device.hpp", "ws_kernels.hpp", "ws_batch.hpp", "wavestep.hip"):
+    for f in ("ws_device.hpp", "ws_kernels.hpp", "ws_batch.hpp"):
         h.update(open(os.path.join(ROOT, "paper_1611_05984_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -185,7 +185,7 @@ ws_status ws_query(ws_domain *d, void *stream, int64_t *step, double *t, int32_t
  * ws_profile_collect synchronizes `stream`, adds each kernel class's summed
  * duration (ms) and launch count into total_ms[k] / launches[k] for
  * k < n (classes WS_K_*), and clears the recorded events. */
-enum { WS_K_PREDICTOR = 0, WS_K_CORRECTOR = 1, WS_K_REDUCE = 2, WS_K_PCR = 3, WS_K_EXPAND = 4,
+enum { WS_K_PREDICTOR = 0, WS_K_CORRECTOR = 1, WS_K_REDUCE = 2, WS_K_SOLVE = 3, WS_K_EXPAND = 4,
        WS_K_COUNT = 5 };
 ws_status ws_profile_enable(ws_domain *d, int32_t on);
 ws_status ws_profile_collect(ws_domain *d, void *stream, double *total_ms, int64_t *launches,

@@ -851,7 +851,7 @@ static ws_status run_pass(ws_domain *d, const StencilArgs &sa, const SolveArgs &
         hipLaunchKernelGGL(k_reduce, tiles(d), dim3(NT), 0, st, so);
     }
     {
-        ProfScope p(d, st, WS_K_PCR);
+        ProfScope p(d, st, WS_K_SOLVE);
         launch_reduced(d, st, so);
     }
     {

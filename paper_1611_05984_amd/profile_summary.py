@@ -61,7 +61,7 @@ def short(name):
 
 def source_hash(root):
     h = hashlib.sha256()
-    for f in ("ws_device.hpp", "ws_kernels.hpp", "ws_batch.hpp", "wavestep.hip"):
+    for f in ("ws_device.hpp", "ws_kernels.hpp", "ws_batch.hpp"):
         h.update(open(os.path.join(root, "paper_1611_05984_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
