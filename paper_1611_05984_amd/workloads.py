@@ -253,3 +253,48 @@ def session_workload(s: Session) -> Workload:
     z = beach_or_flat(s.nx, s.nx, dx, s.depth, s.slope)
     return Workload("session_%d" % s.nx, s.nx, s.nx, dx, dx, courant_dt(s.courant, dx, s.depth), z,
                     walls(), steps=s.steps)
+
+
+# ------------------------------------------------- sec. 4.2 and 4.3 setups
+def whalin(nx: int = 2000, ny: int = 65, amp: float = 0.0075, period: float = 2.0,
+           dt: float = 0.001, steps: int = 20000) -> Workload:
+    """Semicircular shoal (sec. 4.2): 35 m x 6.096 m on nx x ny cells, bottom of
+    eq. 37 as heights above the tank floor with the still water 0.4572 m above
+    it (depth 0.4572 m falling to 0.1524 m over the shoal), west sine maker
+    (a, T), 5 m sponge east, walls north and south, fixed dt.  Eq. 37's middle
+    branch is read as (x - 10.67 + G)/25: as printed it falls below the floor
+    instead of rising to 0.3048 m at x = 18.29 - G.  No random draws."""
+    Lx, Ly, h0 = 35.0, 6.096, 0.4572
+    dx, dy = Lx / nx, Ly / ny
+    X = np.arange(nx + 1)[None, :] * dx
+    Y = np.arange(ny + 1)[:, None] * dy
+    Gy = np.sqrt(np.clip(Y * (Ly - Y), 0.0, None))
+    zf = np.where(X < 10.67 - Gy, 0.0, np.where(X < 18.29 - Gy, (X - 10.67 + Gy) / 25.0, 0.3048))
+    z = zf - h0
+    sides = walls()
+    sides[WEST] = Side(WAVES, 2, [amp], [period], [0.0], [0.0])
+    sides[EAST] = Side(SPONGE, int(round(5.0 / dx)))
+    return Workload("whalin_%dx%d" % (nx, ny), nx, ny, dx, dy, dt, z, sides, steps=steps)
+
+
+def conical_island(n: int = 601, h_over_d: float = 0.09, depth: float = 0.32, dt: float = 0.005,
+                   x0: float = 5.0, sponge_m: float = 2.0, steps: int = 4000) -> Workload:
+    """Solitary wave on a conical island (sec. 4.3): 30 m x 30 m on n x n cells,
+    depth 0.32 m, island centred, base diameter 7.2 m, side slope 1/4 (height
+    above the floor (3.6 - r)/4, flat top at 0.625 m above the floor, i.e.
+    radius 1.1 m: the paper gives diameter and slope only), soliton H = h/d *
+    depth with its crest along y at x0, sponges west and east (width sponge_m),
+    walls north and south, fixed dt.  No random draws."""
+    L = 30.0
+    dx = L / n
+    X = np.arange(n + 1)[None, :] * dx - 0.5 * L
+    Y = np.arange(n + 1)[:, None] * dx - 0.5 * L
+    r = np.sqrt(X * X + Y * Y)
+    above = np.clip((3.6 - r) / 4.0, 0.0, 0.625)
+    z = -depth + above
+    sides = walls()
+    w = int(round(sponge_m / dx))
+    sides[WEST] = Side(SPONGE, w)
+    sides[EAST] = Side(SPONGE, w)
+    return Workload("conical_%dx%d_H%.2f" % (n, n, h_over_d), n, n, dx, dx, dt, z, sides,
+                    solitary=[(h_over_d * depth, 0.0, x0, 0.5 * L)], steps=steps)
