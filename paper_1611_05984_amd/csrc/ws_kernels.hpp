@@ -365,13 +365,40 @@ __device__ __forceinline__ float ghost_change(const SolveArgs &A, int side, int 
 }
 
 // Stage the tile's corner and cell depths in LDS.
-__device__ void load_depths(const Dom &d, SolveTile &s, int i0, int j0) {
-    for (int k = threadIdx.x; k < (TX + 3) * (TY + 3); k += NT) {
-        const int lx = k % (TX + 3), ly = k / (TX + 3);
-        s.cz[ly][lx] = corner_D(d, i0 + lx - 1, j0 + ly - 1);
+// Stage a tile: its two right-hand-side fields and the corner depths around
+// it, all loads issued before any LDS store so that they share one memory
+// latency, then the cell depths from the corners.
+constexpr int CPT = TX * TY / NT;                      // tile cells per thread
+constexpr int ZPT = ((TX + 3) * (TY + 3) + NT - 1) / NT;  // corner values per thread
+__device__ __forceinline__ void stage_tile(const SolveArgs &A, SolveTile &s, int i0, int j0) {
+    const Dom &d = A.d;
+    const int tid = threadIdx.x;
+    float vx[CPT], vy[CPT], vz[ZPT];
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+        const int k = tid + m * NT, cx = k % TX, cy = k / TX;
+        const size_t o = (size_t)(j0 + cy) * d.pitch + i0 + cx;
+        vx[m] = A.rx[o];
+        vy[m] = A.ry[o];
+    }
+#pragma unroll
+    for (int m = 0; m < ZPT; ++m) {
+        const int k = tid + m * NT, lx = k % (TX + 3), ly = k / (TX + 3);
+        vz[m] = k < (TX + 3) * (TY + 3) ? corner_D(d, i0 + lx - 1, j0 + ly - 1) : 0.f;
+    }
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+        const int k = tid + m * NT, cx = k % TX, cy = k / TX;
+        s.rx[cy][cx] = vx[m];
+        s.ry[cy][cx] = vy[m];
+    }
+#pragma unroll
+    for (int m = 0; m < ZPT; ++m) {
+        const int k = tid + m * NT, lx = k % (TX + 3), ly = k / (TX + 3);
+        if (k < (TX + 3) * (TY + 3)) s.cz[ly][lx] = vz[m];
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < (TX + 2) * (TY + 2); k += NT) {
+    for (int k = tid; k < (TX + 2) * (TY + 2); k += NT) {
         const int lx = k % (TX + 2), ly = k / (TX + 2);
         s.dc[ly][lx] = 0.25f * ((s.cz[ly][lx] + s.cz[ly][lx + 1]) + (s.cz[ly + 1][lx] + s.cz[ly + 1][lx + 1]));
     }
@@ -496,13 +523,7 @@ __device__ __forceinline__ void reduce_body(const SolveArgs &A, SolveTile &s, in
     const Dom &d = A.d;
     const int tid = threadIdx.x;
     const int i0 = bx * TX, j0 = by * TY;
-    for (int k = tid; k < TX * TY; k += NT) {
-        const int cx = k % TX, cy = k / TX;
-        const size_t o = (size_t)(j0 + cy) * d.pitch + i0 + cx;
-        s.rx[cy][cx] = A.rx[o];
-        s.ry[cy][cx] = A.ry[o];
-    }
-    load_depths(d, s, i0, j0);
+    stage_tile(A, s, i0, j0);
     if (tid < 64) {
         const int row = tid % 16, seg = tid / 16, k0 = seg * MX;
         float a[MX], b[MX], c[MX];
@@ -772,14 +793,7 @@ __device__ __forceinline__ void expand_body(const SolveArgs &A, SolveTile &s, in
     const Dom &d = A.d;
     const int tid = threadIdx.x;
     const int i0 = bx * TX, j0 = by * TY;
-    for (int k = tid; k < TX * TY; k += NT) {
-        const int cx = k % TX, cy = k / TX;
-        const size_t o = (size_t)(j0 + cy) * d.pitch + i0 + cx;
-        s.rx[cy][cx] = A.rx[o];
-        s.ry[cy][cx] = A.ry[o];
-    }
-    load_depths(d, s, i0, j0);
-    constexpr int CPT = TX * TY / NT;  // epilogue cells per thread
+    // epilogue inputs first: in flight while the tile is staged
     float pre_e[CPT], pre_p[CPT], pre_q[CPT];
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
@@ -790,6 +804,7 @@ __device__ __forceinline__ void expand_body(const SolveArgs &A, SolveTile &s, in
         pre_p[m] = in ? A.pbase[o] : 0.f;
         pre_q[m] = in ? A.qbase[o] : 0.f;
     }
+    stage_tile(A, s, i0, j0);
     if (tid < 64) {
         const int row = tid % 16, seg = tid / 16, k0 = seg * MX;
         const int k = 2 * (bx * (TX / MX) + seg), j = j0 + row;
