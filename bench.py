@@ -35,13 +35,14 @@ TUNING_CACHE = os.path.join(ROOT, "paper_1611_05984_amd", "tuning_cache.txt")
 #              sides (factored solve)                       -> 3 + 2 + 1 or 0.25
 #   reduced solve: PCR reads the equations, writes the solutions: 1 + 0.25;
 #              lane Thomas also writes and rereads its sweep values: 1 + 0.5 +
-#              0.5 + 0.25; factored solve reads the right-hand sides and three
-#              factors, writes the solutions: 0.25 + 0.75 + 0.25
+#              0.5 + 0.25; the factored solves (one- or two-ended) read the
+#              right-hand sides and three factors, write the solutions:
+#              0.25 + 0.75 + 0.25
 #   expand:    reads eliminated values (2), P^n, Q^n, eta, depth, end values;
 #              writes P, Q                                  -> 6.25 + 2
 def alg_words(solver):
-    reduce_w = 5.25 if solver == 2 else 6.0
-    solve_w = {0: 1.25, 1: 2.25, 2: 1.25}[solver]
+    reduce_w = 5.25 if solver in (2, 3) else 6.0
+    solve_w = {0: 1.25, 1: 2.25, 2: 1.25, 3: 1.25}[solver]
     return {"k_stencil[predictor]": 23.0, "k_stencil[corrector]": 10.0,
             "k_reduce": reduce_w, "reduced_solve": solve_w, "k_expand": 8.25}
 
@@ -156,7 +157,7 @@ def batched_vs_plain(args, torch, ws, wl):
             "batched_over_plain_eager": (cells * n / t_b) / (cells * n / t_p),
             "unit": "cell-updates/s", "healthy": all(h == 0 for h in health),
             "batch_tuning": {"stencil_rows": tuning[0], "pcr_threads": tuning[1],
-                             "solver": ("pcr", "thomas", "lu")[tuning[2]]}}
+                             "solver": ("pcr", "thomas", "lu", "lu2")[tuning[2]]}}
 
 
 def serving(args):
@@ -255,7 +256,7 @@ def main():
     dom_func = max(fsum, key=lambda f: fsum[f][0])
     # kernel symbol as the profiler names it (template instance of the tuned shape)
     dom_name = {"k_stencil": "k_stencil<%d>" % tuning[0],
-                "reduced_solve": ("k_pcr", "k_thomas", "k_lu_solve")[tuning[2]]}.get(dom_func, dom_func)
+                "reduced_solve": ("k_pcr", "k_thomas", "k_lu_solve", "k_lu2_solve")[tuning[2]]}.get(dom_func, dom_func)
     dom_ms, dom_n, dom_words = fsum[dom_func]
     avg_s = dom_ms / dom_n / 1e3
     alg_bytes = dom_words / dom_n * 4.0 * cells
@@ -289,7 +290,7 @@ def main():
         "config": {"workload": w.name + "_jonswap64_sponge64", "nx": w.nx, "ny": w.ny,
                    "dx_m": w.dx, "dt_s": w.dt, "n_corr": 2, "fstar_extrap": 1,
                    "tuning": {"stencil_rows": tuning[0], "pcr_threads": tuning[1],
-                              "solver": ("pcr", "thomas", "lu")[tuning[2]]},
+                              "solver": ("pcr", "thomas", "lu", "lu2")[tuning[2]]},
                    "boundaries": "W waves(64 comps) / E sponge(64) / N,S walls"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

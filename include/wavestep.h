@@ -239,10 +239,12 @@ ws_status ws_batch_status(ws_batch *b, int32_t slot, int64_t *step, double *t, i
  * chain per lane) or by factors computed once per bathymetry and boundary
  * set (WS_SOLVE_LU: the same Thomas arithmetic, two multiply-adds per unknown
  * per pass, system-interleaved storage; refactored automatically after
- * ws_set_boundary, terrain edits and ws_restore).  Rows and threads do not
- * change results (bitwise); THOMAS and LU give the same bits; PCR rounds the
- * reduced solve differently. */
-enum { WS_SOLVE_PCR = 0, WS_SOLVE_THOMAS = 1, WS_SOLVE_LU = 2 };  /* reduced-system strategy */
+ * ws_set_boundary, terrain edits and ws_restore) or by such factors of a
+ * two-ended elimination (WS_SOLVE_LU2: two lanes per system meeting in the
+ * middle, half the dependent chain).  Rows and threads do not change results
+ * (bitwise); THOMAS and LU give the same bits; PCR and LU2 round the reduced
+ * solve differently. */
+enum { WS_SOLVE_PCR = 0, WS_SOLVE_THOMAS = 1, WS_SOLVE_LU = 2, WS_SOLVE_LU2 = 3 };  /* reduced-system strategy */
 typedef struct {
     int32_t stencil_rows;
     int32_t pcr_threads;

@@ -50,8 +50,9 @@ struct ws_domain {
     float *hist[3][5];             // [slot][E, F, G, F*, G*]
     float4 *redx, *redy;
     float *solx, *soly;
-    float *lux, *luy;              // static factors of the reduced systems (factored solve)
+    float *lux, *luy;              // static factors of the reduced systems (factored solves)
     bool lu_valid;
+    int lu_kind;                   // solver the factors were computed for
     float *ghost[2];               // wave-maker ghosts at t^n, t^{n+1}
     int gl;                        // ghost positions per layer
     double *tab[4];                // wave tables
@@ -800,7 +801,7 @@ static void pass_args(const ws_domain *d, const Dom &m, bool euler, int cur, int
     so.health = d->health;
     so.lux = d->lux;
     so.luy = d->luy;
-    so.layout = d->solver == WS_SOLVE_LU ? 1 : 0;
+    so.layout = (d->solver == WS_SOLVE_LU || d->solver == WS_SOLVE_LU2) ? 1 : 0;
     so.sponge = p == K ? 1 : 0;
 }
 
@@ -811,26 +812,34 @@ static bool has_makers(const ws_domain *d) {
 }
 
 static int solve_waves(const ws_domain *d) { return (d->g.ny + 63) / 64 + (d->g.nx + 63) / 64; }
+static int solve2_waves(int nx, int ny) { return (2 * ny + 63) / 64 + (2 * nx + 63) / 64; }
+static bool factored(int solver) { return solver == WS_SOLVE_LU || solver == WS_SOLVE_LU2; }
 
 // Factors of the reduced systems for the factored solve, when stale: a
 // coefficient-mode reduction (contiguous equations; its right-hand sides and
 // eliminated values are scratch) and one factorization sweep per system.
 static ws_status ensure_factors(ws_domain *d, hipStream_t st) {
-    if (d->solver != WS_SOLVE_LU || d->lu_valid) return WS_OK;
+    if (!factored(d->solver) || (d->lu_valid && d->lu_kind == d->solver)) return WS_OK;
     StencilArgs sa;
     SolveArgs so;
     pass_args(d, make_dom(d), false, d->cur, 0, 0, sa, so);
     so.layout = 0;
     hipLaunchKernelGGL(k_reduce, tiles(d), dim3(NT), 0, st, so);
-    hipLaunchKernelGGL(k_lu_factor, dim3(solve_waves(d)), dim3(64), 0, st, so, d->lux, d->luy);
+    if (d->solver == WS_SOLVE_LU2)
+        hipLaunchKernelGGL(k_lu2_factor, dim3(solve_waves(d)), dim3(64), 0, st, so, d->lux, d->luy);
+    else
+        hipLaunchKernelGGL(k_lu_factor, dim3(solve_waves(d)), dim3(64), 0, st, so, d->lux, d->luy);
     HIPCHK(hipGetLastError());
     d->lu_valid = true;
+    d->lu_kind = d->solver;
     return WS_OK;
 }
 
 // The reduced row and column systems, by the domain's strategy.
 static void launch_reduced(const ws_domain *d, hipStream_t st, const SolveArgs &so) {
-    if (d->solver == WS_SOLVE_LU) {
+    if (d->solver == WS_SOLVE_LU2) {
+        hipLaunchKernelGGL(k_lu2_solve, dim3(solve2_waves(d->g.nx, d->g.ny)), dim3(64), 0, st, so);
+    } else if (d->solver == WS_SOLVE_LU) {
         hipLaunchKernelGGL(k_lu_solve, dim3(solve_waves(d)), dim3(64), 0, st, so);
     } else if (d->solver == WS_SOLVE_THOMAS) {
         const int waves = (d->g.ny + 63) / 64 + (d->g.nx + 63) / 64;
@@ -1046,7 +1055,9 @@ static ws_status batch_upload(ws_batch *b) {
         const BatchDesc &D = desc[k];
         pre[0][k + 1] = pre[0][k] + D.sgx * D.sgy;
         pre[1][k + 1] = pre[1][k] + D.tgx * D.tgy;
-        pre[2][k + 1] = pre[2][k] + (b->solver != WS_SOLVE_PCR ? (D.d.ny + 63) / 64 + (D.d.nx + 63) / 64 : D.nsys);
+        pre[2][k + 1] = pre[2][k] + (b->solver == WS_SOLVE_LU2   ? solve2_waves(D.d.nx, D.d.ny)
+                                     : b->solver != WS_SOLVE_PCR ? (D.d.ny + 63) / 64 + (D.d.nx + 63) / 64
+                                                                 : D.nsys);
         pre[3][k + 1] = pre[3][k] + (D.makers ? (8 * D.d.gl * GHL + 255) / 256 : 0);
         maxK = D.K > maxK ? D.K : maxK;
         const int nr = d->nu > d->nv ? d->nu : d->nv;
@@ -1083,7 +1094,9 @@ static ws_status batch_step(ws_batch *b, hipStream_t st) {
 #undef L4
         hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NT), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, p);
         const size_t shm = sizeof(float4) * b->nred;
-        if (b->solver == WS_SOLVE_LU)
+        if (b->solver == WS_SOLVE_LU2)
+            hipLaunchKernelGGL(kb_lu2_solve, pg, dim3(64), 0, st, b->d_desc, b->d_state, b->d_pre[2], n, p);
+        else if (b->solver == WS_SOLVE_LU)
             hipLaunchKernelGGL(kb_lu_solve, pg, dim3(64), 0, st, b->d_desc, b->d_state, b->d_pre[2], n, p);
         else if (b->solver == WS_SOLVE_THOMAS)
             hipLaunchKernelGGL(kb_thomas, pg, dim3(64), 0, st, b->d_desc, b->d_state, b->d_pre[2], n, p);
@@ -1239,7 +1252,7 @@ static bool tuning_ok(const ws_tuning *t) {
     return t && (t->stencil_rows == 8 || t->stencil_rows == 16 || t->stencil_rows == 24 ||
                  t->stencil_rows == 32 || t->stencil_rows == 48 || t->stencil_rows == 64) &&
            (t->pcr_threads == 64 || t->pcr_threads == 128 || t->pcr_threads == 256) &&
-           (t->solver == WS_SOLVE_PCR || t->solver == WS_SOLVE_THOMAS || t->solver == WS_SOLVE_LU);
+           (t->solver >= WS_SOLVE_PCR && t->solver <= WS_SOLVE_LU2);
 }
 
 extern "C" ws_status ws_get_tuning(const ws_domain *d, ws_tuning *out) {
@@ -1397,8 +1410,27 @@ extern "C" ws_status ws_tune(ws_domain *d, const char *cache_path, void *stream,
             HIPCHK(hipEventElapsedTime(&ms, e0, e1));
             total += ms;
         }
-        d->solver = keep;
         if (total < best_p) { best_p = total; best.solver = WS_SOLVE_LU; }
+        // two-ended factored solve
+        d->solver = WS_SOLVE_LU2;
+        r = ensure_factors(d, st);
+        if (r != WS_OK) {
+            d->solver = keep;
+            return r;
+        }
+        total = 0.f;
+        for (int k = 0; k < reps; ++k) {
+            hipLaunchKernelGGL(k_reduce, tiles(d), dim3(NT), 0, st, s1);
+            HIPCHK(hipEventRecord(e0, st));
+            hipLaunchKernelGGL(k_lu2_solve, dim3(solve2_waves(d->g.nx, d->g.ny)), dim3(64), 0, st, s1);
+            HIPCHK(hipEventRecord(e1, st));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            total += ms;
+        }
+        d->solver = keep;
+        if (total < best_p) { best_p = total; best.solver = WS_SOLVE_LU2; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1509,7 +1541,27 @@ extern "C" ws_status ws_batch_tune(ws_batch *b, void *stream, ws_tuning *out) {
             (void)hipEventElapsedTime(&ms, e0, e1);
             if (k > 0) total += ms;
         }
-        if (total < best) best_solver = WS_SOLVE_LU;
+        if (total < best) {
+            best = total;
+            best_solver = WS_SOLVE_LU;
+        }
+        b->solver = WS_SOLVE_LU2;  // trial
+        b->dirty = true;
+        if ((r = batch_upload(b)) != WS_OK) return r;
+        for (int sl : b->order)
+            if ((r = ensure_factors(b->slots[sl], st)) != WS_OK) return r;
+        total = 0.f;
+        for (int k = 0; k < 4; ++k) {
+            hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NT), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, 1);
+            (void)hipEventRecord(e0, st);
+            hipLaunchKernelGGL(kb_lu2_solve, dim3(b->total[2]), dim3(64), 0, st, b->d_desc, b->d_state, b->d_pre[2], n, 1);
+            (void)hipEventRecord(e1, st);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (k > 0) total += ms;
+        }
+        if (total < best) best_solver = WS_SOLVE_LU2;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -175,6 +175,18 @@ __global__ __launch_bounds__(64) void kb_lu_solve(const BatchDesc *__restrict__ 
     lu_solve_body(A, b - prefix[dm], threadIdx.x);
 }
 
+// Two-ended factored solves: lane pairs per system (see lu2_solve_body).
+__global__ __launch_bounds__(64) void kb_lu2_solve(const BatchDesc *__restrict__ descs,
+                                                   const BatchState *__restrict__ states,
+                                                   const int *__restrict__ prefix, int ndom, int p) {
+    const int b = blockIdx.x, dm = find_dom(prefix, ndom, b);
+    const BatchDesc &D = descs[dm];
+    const int v = variant(D, states[dm], p);
+    if (v < 0) return;
+    const SolveArgs A = load_params(D.so + v);
+    lu2_solve_body(A, b - prefix[dm], threadIdx.x);
+}
+
 // Wave-maker ghosts of t^n (which = 0) and t^{n+1} (which = 1); 256 threads
 // per block, 8 gl GHL threads per domain with wave makers.
 __global__ void kb_ghosts(const BatchDesc *descs, const BatchState *states, const int *prefix, int ndom,

@@ -690,21 +690,133 @@ __device__ __forceinline__ void lu_solve_lane(int N, const float *r, const float
     }
 }
 
+// Two-ended factored solve: the same systems eliminated from both ends at
+// once ("twisted" factorization), two lanes per system, so each lane's
+// dependent chain is half as long.  Rows k < h = N/2 keep the forward
+// factors (a_k, 1/pivot_k) and c'_k of the one-ended solve; rows k >= h are
+// eliminated upward from the last row: pivot'_k = b_k - c_k a'_{k+1},
+// a'_k = a_k / pivot'_k, stored as (c_k, 1/pivot'_k) and a'_k.  The two
+// half-sweeps meet in a 2 x 2 system for x_{h-1}, x_h.
+__device__ __forceinline__ void lu2_factor_lane(int N, const float4 *eq, float2 *fai, float *fcp, size_t stride) {
+    const int h = N / 2;
+    float cp = 0.f;
+    for (int k = 0; k < h; ++k) {
+        const float4 e = eq[k];
+        const float inv = frcp(e.y - e.x * cp);
+        cp = e.z * inv;
+        fai[k * stride] = make_float2(e.x, inv);
+        fcp[k * stride] = cp;
+    }
+    float ap = 0.f;
+    for (int k = N - 1; k >= h; --k) {
+        const float4 e = eq[k];
+        const float inv = frcp(e.y - e.z * ap);
+        ap = e.x * inv;
+        fai[k * stride] = make_float2(e.z, inv);
+        fcp[k * stride] = ap;
+    }
+}
+
+// acc <- (r_k - f.x acc) f.y over `count` unknowns from k0 in direction dir,
+// each result stored to x_k; loads in blocks as in lu_solve_lane.
+__device__ __forceinline__ float lu2_sweep(int k0, int dir, int count, const float *r, const float2 *fai, float *x,
+                                           size_t stride) {
+    float acc = 0.f;
+    int i = 0;
+    for (; i + LU_U <= count; i += LU_U) {
+        float rr[LU_U];
+        float2 ai[LU_U];
+#pragma unroll
+        for (int u = 0; u < LU_U; ++u) {
+            const size_t o = (size_t)(k0 + dir * (i + u)) * stride;
+            rr[u] = r[o];
+            ai[u] = fai[o];
+        }
+#pragma unroll
+        for (int u = 0; u < LU_U; ++u) {
+            acc = (rr[u] - ai[u].x * acc) * ai[u].y;
+            x[(size_t)(k0 + dir * (i + u)) * stride] = acc;
+        }
+    }
+    for (; i < count; ++i) {
+        const size_t o = (size_t)(k0 + dir * i) * stride;
+        const float2 ai = fai[o];
+        acc = (r[o] - ai.x * acc) * ai.y;
+        x[o] = acc;
+    }
+    return acc;
+}
+
+// v <- x_k - c_k v over `count` unknowns from k0 in direction dir.
+__device__ __forceinline__ void lu2_back(float v, int k0, int dir, int count, const float *fcp, float *x,
+                                         size_t stride) {
+    int i = 0;
+    for (; i + LU_U <= count; i += LU_U) {
+        float xx[LU_U], cc[LU_U];
+#pragma unroll
+        for (int u = 0; u < LU_U; ++u) {
+            const size_t o = (size_t)(k0 + dir * (i + u)) * stride;
+            xx[u] = x[o];
+            cc[u] = fcp[o];
+        }
+#pragma unroll
+        for (int u = 0; u < LU_U; ++u) {
+            v = xx[u] - cc[u] * v;
+            x[(size_t)(k0 + dir * (i + u)) * stride] = v;
+        }
+    }
+    for (; i < count; ++i) {
+        const size_t o = (size_t)(k0 + dir * i) * stride;
+        v = x[o] - fcp[o] * v;
+        x[o] = v;
+    }
+}
+
+// One lane of a lane pair (top: rows 0 .. h-1, bottom: rows h .. N-1).
+__device__ __forceinline__ void lu2_solve_lane(int N, bool top, const float *r, const float2 *fai,
+                                               const float *fcp, float *x, size_t stride) {
+    const int h = N / 2;
+    const float acc = top ? lu2_sweep(0, 1, h, r, fai, x, stride) : lu2_sweep(N - 1, -1, N - h, r, fai, x, stride);
+    const float cm = fcp[(size_t)(top ? h - 1 : h) * stride];  // c'_{h-1} (top) or a'_h (bottom)
+    const float acc_o = __shfl_xor(acc, 1), cm_o = __shfl_xor(cm, 1);
+    const float dp = top ? acc : acc_o, cp = top ? cm : cm_o;   // x_{h-1} + cp x_h = dp
+    const float eq = top ? acc_o : acc, ap = top ? cm_o : cm;   // x_h + ap x_{h-1} = eq
+    const float xl = (dp - cp * eq) * frcp(1.f - cp * ap);      // x_{h-1}
+    const float xh = eq - ap * xl;                              // x_h
+    if (top) {
+        x[(size_t)(h - 1) * stride] = xl;
+        lu2_back(xl, h - 2, -1, h - 1, fcp, x, stride);
+    } else {
+        x[(size_t)h * stride] = xh;
+        lu2_back(xh, h + 1, 1, N - h - 1, fcp, x, stride);
+    }
+}
+
 // Waves 0 .. xw-1 take the row systems, the rest the column systems.
-__device__ __forceinline__ void lu_factor_body(const SolveArgs &A, float *lux, float *luy, int wave, int lane) {
+__device__ __forceinline__ void lu_factor_body_impl(const SolveArgs &A, float *lux, float *luy, int wave, int lane,
+                                                    bool two_ended) {
     const Dom &d = A.d;
     const int xw = (d.ny + 63) / 64;
     if (wave < xw) {
         const int j = wave * 64 + lane;
         const size_t n = (size_t)d.nu * d.ny;
-        if (j < d.ny)
-            lu_factor_lane(d.nu, A.redx + (size_t)j * d.nu, reinterpret_cast<float2 *>(lux) + j, lux + 2 * n + j, d.ny);
+        if (j < d.ny) {
+            float2 *fai = reinterpret_cast<float2 *>(lux) + j;
+            if (two_ended) lu2_factor_lane(d.nu, A.redx + (size_t)j * d.nu, fai, lux + 2 * n + j, d.ny);
+            else lu_factor_lane(d.nu, A.redx + (size_t)j * d.nu, fai, lux + 2 * n + j, d.ny);
+        }
     } else {
         const int i = (wave - xw) * 64 + lane;
         const size_t n = (size_t)d.nv * d.nx;
-        if (i < d.nx)
-            lu_factor_lane(d.nv, A.redy + (size_t)i * d.nv, reinterpret_cast<float2 *>(luy) + i, luy + 2 * n + i, d.nx);
+        if (i < d.nx) {
+            float2 *fai = reinterpret_cast<float2 *>(luy) + i;
+            if (two_ended) lu2_factor_lane(d.nv, A.redy + (size_t)i * d.nv, fai, luy + 2 * n + i, d.nx);
+            else lu_factor_lane(d.nv, A.redy + (size_t)i * d.nv, fai, luy + 2 * n + i, d.nx);
+        }
     }
+}
+__device__ __forceinline__ void lu_factor_body(const SolveArgs &A, float *lux, float *luy, int wave, int lane) {
+    lu_factor_body_impl(A, lux, luy, wave, lane, false);
 }
 
 __device__ __forceinline__ void lu_solve_body(const SolveArgs &A, int wave, int lane) {
@@ -725,10 +837,35 @@ __device__ __forceinline__ void lu_solve_body(const SolveArgs &A, int wave, int 
     }
 }
 
+// Lane pairs (2q: top half, 2q + 1: bottom half) per system; waves
+// 0 .. xw-1 take the row systems, the rest the column systems.
+__device__ __forceinline__ void lu2_solve_body(const SolveArgs &A, int wave, int lane) {
+    const Dom &d = A.d;
+    const int xw = (2 * d.ny + 63) / 64;
+    if (wave < xw) {
+        const int l = wave * 64 + lane, j = l >> 1;
+        const size_t n = (size_t)d.nu * d.ny;
+        if (j < d.ny)
+            lu2_solve_lane(d.nu, (l & 1) == 0, reinterpret_cast<const float *>(A.redx) + j,
+                           reinterpret_cast<const float2 *>(A.lux) + j, A.lux + 2 * n + j, A.solx + j, d.ny);
+    } else {
+        const int l = (wave - xw) * 64 + lane, i = l >> 1;
+        const size_t n = (size_t)d.nv * d.nx;
+        if (i < d.nx)
+            lu2_solve_lane(d.nv, (l & 1) == 0, reinterpret_cast<const float *>(A.redy) + i,
+                           reinterpret_cast<const float2 *>(A.luy) + i, A.luy + 2 * n + i, A.soly + i, d.nx);
+    }
+}
+
+
 __global__ __launch_bounds__(64) void k_lu_factor(SolveArgs A, float *lux, float *luy) {
     lu_factor_body(A, lux, luy, blockIdx.x, threadIdx.x);
 }
 __global__ __launch_bounds__(64) void k_lu_solve(SolveArgs A) { lu_solve_body(A, blockIdx.x, threadIdx.x); }
+__global__ __launch_bounds__(64) void k_lu2_factor(SolveArgs A, float *lux, float *luy) {
+    lu_factor_body_impl(A, lux, luy, blockIdx.x, threadIdx.x, true);
+}
+__global__ __launch_bounds__(64) void k_lu2_solve(SolveArgs A) { lu2_solve_body(A, blockIdx.x, threadIdx.x); }
 
 // Parallel cyclic reduction of one reduced system (rows first, then
 // columns): each thread keeps its equations (k = tid + j * PCR_NT) in

@@ -263,7 +263,7 @@ def test_tunings_identical_results_and_autotuner(tmp_path):
     before = d.state_numpy()
     cache = str(tmp_path / "tune.txt")
     t = d.tune(cache)
-    assert t[0] in (8, 16, 24, 32, 48, 64) and t[1] in (64, 128, 256) and t[2] in (0, 1, 2)
+    assert t[0] in (8, 16, 24, 32, 48, 64) and t[1] in (64, 128, 256) and t[2] in (0, 1, 2, 3)
     assert d.tuning() == t
     after = d.state_numpy()
     assert all(np.array_equal(x, y) for x, y in zip(before, after)) and d.query()[0] == 30
@@ -277,13 +277,13 @@ def test_tunings_identical_results_and_autotuner(tmp_path):
     same(ref, d, "after tuning")
     with pytest.raises(ws.WaveStepError):
         d.set_tuning(40, 128)
-    B = ws.Batch(2)
+    B = ws.Batch(4)
     b = make(w)
     B.set_tuning(24, 64)
     B.attach(b)
     B.advance(20)
     tb = B.tune()                                  # leaves the states alone
-    assert tb[0] in (8, 16, 24, 32, 48, 64) and tb[1] in (64, 128, 256) and tb[2] in (0, 1, 2)
+    assert tb[0] in (8, 16, 24, 32, 48, 64) and tb[1] in (64, 128, 256) and tb[2] in (0, 1, 2, 3)
     B.set_tuning(tb[0], tb[1], ws.SOLVE_PCR)
     B.advance(20)
     B.sync()
@@ -307,4 +307,17 @@ def test_tunings_identical_results_and_autotuner(tmp_path):
     lu2.advance(25)
     B.sync()
     same(lu2, lu2b, "batched factored solve")
+    # two-ended factored solve: rounds differently from the one-ended sweep;
+    # batched equals single-domain bit for bit
+    tw = make(w)
+    twb = make(w)
+    tw.set_tuning(16, 128, ws.SOLVE_LU2)
+    B.set_tuning(16, 128, ws.SOLVE_LU2)
+    B.attach(twb)
+    B.advance(25)
+    tw.advance(25)
+    B.sync()
+    same(tw, twb, "batched two-ended factored solve")
+    for x, y in zip(lu2.state_numpy(), tw.state_numpy()):
+        assert np.abs(x - y).max() <= 1e-6 * max(1.0, np.abs(x).max())
     B.close()
