@@ -2,6 +2,7 @@
 // C ABI of include/wavestep.h, and the launch sequence of one step.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -813,6 +814,12 @@ static bool has_makers(const ws_domain *d) {
 
 static int solve_waves(const ws_domain *d) { return (d->g.ny + 63) / 64 + (d->g.nx + 63) / 64; }
 static int solve2_waves(int nx, int ny) { return (2 * ny + 63) / 64 + (2 * nx + 63) / 64; }
+// Waves per workgroup of the one-ended factored solve's workgroup form (LUR
+// unknowns a wave), or 0 where the longest reduced system is too long for it
+// and the lane-per-system sweep runs instead.
+static int luw_waves(int nred) { return nred <= LUR * LUW_MAX ? (nred + LUR - 1) / LUR : 0; }
+static int luw_groups(int nx, int ny) { return (ny + 63) / 64 + (nx + 63) / 64; }
+static int nred_of(const ws_domain *d) { return d->nu > d->nv ? d->nu : d->nv; }
 static bool factored(int solver) { return solver == WS_SOLVE_LU || solver == WS_SOLVE_LU2; }
 
 // Factors of the reduced systems for the factored solve, when stale: a
@@ -840,7 +847,11 @@ static void launch_reduced(const ws_domain *d, hipStream_t st, const SolveArgs &
     if (d->solver == WS_SOLVE_LU2) {
         hipLaunchKernelGGL(k_lu2_solve, dim3(solve2_waves(d->g.nx, d->g.ny)), dim3(64), 0, st, so);
     } else if (d->solver == WS_SOLVE_LU) {
-        hipLaunchKernelGGL(k_lu_solve, dim3(solve_waves(d)), dim3(64), 0, st, so);
+        const int G = luw_waves(nred_of(d));
+        if (G)
+            hipLaunchKernelGGL(k_luw_solve, dim3(luw_groups(d->g.nx, d->g.ny)), dim3(64 * G), 0, st, so);
+        else
+            hipLaunchKernelGGL(k_lu_solve, dim3(solve_waves(d)), dim3(64), 0, st, so);
     } else if (d->solver == WS_SOLVE_THOMAS) {
         const int waves = (d->g.ny + 63) / 64 + (d->g.nx + 63) / 64;
         hipLaunchKernelGGL(k_thomas, dim3(waves), dim3(64), 0, st, so);
@@ -1035,6 +1046,7 @@ static ws_status batch_upload(ws_batch *b) {
     std::vector<int> pre[4];
     for (int q = 0; q < 4; ++q) pre[q].assign(n + 1, 0);
     int maxK = 0, nred = 0;
+    for (int k = 0; k < n; ++k) nred = std::max(nred, nred_of(b->slots[order[k]]));
     for (int k = 0; k < n; ++k) {
         ws_domain *d = b->slots[order[k]];
         if (d->solver != b->solver) {  // the batch's solve strategy (and layout) applies
@@ -1055,13 +1067,11 @@ static ws_status batch_upload(ws_batch *b) {
         const BatchDesc &D = desc[k];
         pre[0][k + 1] = pre[0][k] + D.sgx * D.sgy;
         pre[1][k + 1] = pre[1][k] + D.tgx * D.tgy;
-        pre[2][k + 1] = pre[2][k] + (b->solver == WS_SOLVE_LU2   ? solve2_waves(D.d.nx, D.d.ny)
-                                     : b->solver != WS_SOLVE_PCR ? (D.d.ny + 63) / 64 + (D.d.nx + 63) / 64
-                                                                 : D.nsys);
+        pre[2][k + 1] = pre[2][k] + (b->solver == WS_SOLVE_LU2      ? solve2_waves(D.d.nx, D.d.ny)
+                                     : b->solver != WS_SOLVE_PCR    ? (D.d.ny + 63) / 64 + (D.d.nx + 63) / 64
+                                                                    : D.nsys);
         pre[3][k + 1] = pre[3][k] + (D.makers ? (8 * D.d.gl * GHL + 255) / 256 : 0);
         maxK = D.K > maxK ? D.K : maxK;
-        const int nr = d->nu > d->nv ? d->nu : d->nv;
-        nred = nr > nred ? nr : nred;
     }
     if (n) {
         HIPCHK(hipMemcpy(b->d_desc, desc.data(), sizeof(BatchDesc) * n, hipMemcpyHostToDevice));
@@ -1097,7 +1107,10 @@ static ws_status batch_step(ws_batch *b, hipStream_t st) {
         if (b->solver == WS_SOLVE_LU2)
             hipLaunchKernelGGL(kb_lu2_solve, pg, dim3(64), 0, st, b->d_desc, b->d_state, b->d_pre[2], n, p);
         else if (b->solver == WS_SOLVE_LU)
-            hipLaunchKernelGGL(kb_lu_solve, pg, dim3(64), 0, st, b->d_desc, b->d_state, b->d_pre[2], n, p);
+            if (const int G = luw_waves(b->nred))
+                hipLaunchKernelGGL(kb_luw_solve, pg, dim3(64 * G), 0, st, b->d_desc, b->d_state, b->d_pre[2], n, p);
+            else
+                hipLaunchKernelGGL(kb_lu_solve, pg, dim3(64), 0, st, b->d_desc, b->d_state, b->d_pre[2], n, p);
         else if (b->solver == WS_SOLVE_THOMAS)
             hipLaunchKernelGGL(kb_thomas, pg, dim3(64), 0, st, b->d_desc, b->d_state, b->d_pre[2], n, p);
         else
@@ -1403,7 +1416,7 @@ extern "C" ws_status ws_tune(ws_domain *d, const char *cache_path, void *stream,
         for (int k = 0; k < reps; ++k) {
             hipLaunchKernelGGL(k_reduce, tiles(d), dim3(NT), 0, st, s1);
             HIPCHK(hipEventRecord(e0, st));
-            hipLaunchKernelGGL(k_lu_solve, dim3(solve_waves(d)), dim3(64), 0, st, s1);
+            launch_reduced(d, st, s1);
             HIPCHK(hipEventRecord(e1, st));
             HIPCHK(hipEventSynchronize(e1));
             float ms = 0.f;
@@ -1534,7 +1547,12 @@ extern "C" ws_status ws_batch_tune(ws_batch *b, void *stream, ws_tuning *out) {
         for (int k = 0; k < 4; ++k) {
             hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NT), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, 1);
             (void)hipEventRecord(e0, st);
-            hipLaunchKernelGGL(kb_lu_solve, dim3(b->total[2]), dim3(64), 0, st, b->d_desc, b->d_state, b->d_pre[2], n, 1);
+            if (const int G = luw_waves(b->nred))
+                hipLaunchKernelGGL(kb_luw_solve, dim3(b->total[2]), dim3(64 * G), 0, st, b->d_desc, b->d_state,
+                                   b->d_pre[2], n, 1);
+            else
+                hipLaunchKernelGGL(kb_lu_solve, dim3(b->total[2]), dim3(64), 0, st, b->d_desc, b->d_state,
+                                   b->d_pre[2], n, 1);
             (void)hipEventRecord(e1, st);
             (void)hipEventSynchronize(e1);
             float ms = 0.f;

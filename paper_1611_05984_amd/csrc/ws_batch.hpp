@@ -175,6 +175,20 @@ __global__ __launch_bounds__(64) void kb_lu_solve(const BatchDesc *__restrict__ 
     lu_solve_body(A, b - prefix[dm], threadIdx.x);
 }
 
+// One-ended factored solves, workgroup form (see luw_solve_body); every
+// workgroup of a paused domain leaves at once, before any barrier.
+__global__ __launch_bounds__(64 * LUW_MAX) void kb_luw_solve(const BatchDesc *__restrict__ descs,
+                                                             const BatchState *__restrict__ states,
+                                                             const int *__restrict__ prefix, int ndom, int p) {
+    __shared__ float slot[64];
+    const int b = blockIdx.x, dm = find_dom(prefix, ndom, b);
+    const BatchDesc &D = descs[dm];
+    const int v = variant(D, states[dm], p);
+    if (v < 0) return;
+    const SolveArgs A = load_params(D.so + v);
+    luw_solve_body(A, b - prefix[dm], slot);
+}
+
 // Two-ended factored solves: lane pairs per system (see lu2_solve_body).
 __global__ __launch_bounds__(64) void kb_lu2_solve(const BatchDesc *__restrict__ descs,
                                                    const BatchState *__restrict__ states,

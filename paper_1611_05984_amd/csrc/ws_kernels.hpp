@@ -819,6 +819,128 @@ __device__ __forceinline__ void lu_factor_body(const SolveArgs &A, float *lux, f
     lu_factor_body_impl(A, lux, luy, wave, lane, false);
 }
 
+// Unknowns of one system per wave in the workgroup form of the factored solve.
+constexpr int LUR = 32;
+constexpr int LUW_MAX = 16;  // waves per workgroup (1024 threads): systems up to LUR x LUW_MAX
+
+// The workgroup form of the one-ended sweeps, for systems of at most
+// LUR x (waves in the workgroup) unknowns: a workgroup takes 64 systems, lane
+// l of every wave system s0 + l, and wave q unknowns q LUR .. q LUR + LUR - 1
+// of all 64, so every load and store covers 64 consecutive systems of one
+// row of the interleaved layout, and the whole system sits in registers
+// after one round trip.  The chain then runs wave by wave, handing the
+// running value on through LDS between workgroup barriers: forward from
+// wave 0, back from the last.  Same operations in the same order as
+// lu_solve_lane (same bits).  Lanes past the last system compute on a copy
+// of it and store nothing, so every wave reaches every barrier.
+// Raw buffer access: a resource (base, size in bytes) in SGPRs, a per-lane
+// byte offset and a wave-uniform byte offset, so that no per-lane 64-bit
+// address is formed or kept; every offset used below is in range.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t bres(const void *p, size_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, unsigned vo, int so) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+}
+__device__ __forceinline__ float2 bld2(__amdgpu_buffer_rsrc_t r, unsigned vo, int so) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0);
+    return make_float2(__uint_as_float(v[0]), __uint_as_float(v[1]));
+}
+__device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, unsigned vo, int so, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, vo, so, 0);
+}
+
+// Workgroup barrier that waits only for the wave's LDS operations: the
+// waves hand each other nothing through global memory here, so loads and
+// stores in flight may stay in flight across it (a full __syncthreads
+// would wait for every one of them at every hand-off).
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+__device__ __forceinline__ void luw_solve(int N, int nsys, int s0, const float *r, const float2 *fai, const float *fcp,
+                                          float *x, float *slot) {
+    const int lane = threadIdx.x & 63;
+    const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int G = blockDim.x >> 6;
+    const int s = min(s0 + lane, nsys - 1);
+    const bool live = s0 + lane < nsys;
+    const int k0 = q * LUR;
+    const size_t n = (size_t)N * nsys;
+    const auto br = bres(r, 4 * n), bf = bres(fai, 8 * n), bc = bres(fcp, 4 * n), bx = bres(x, 4 * n);
+    const unsigned o4 = 4u * (unsigned)s, o8 = 8u * (unsigned)s;
+    auto row = [&](int u) { return min(k0 + u, N - 1) * nsys; };  // wave-uniform
+    // Rows past the system's end get y = 0 and factors (a, 1/pivot) = (-1, 1),
+    // c' = -1, which pass the running value on exactly; the last row gets
+    // c' = 0 (its back step gives x_{N-1} itself).  So every wave runs its
+    // part without conditions.
+    float y[LUR], cc[LUR];
+    float2 ai[LUR];
+#pragma unroll
+    for (int u = 0; u < LUR; ++u) {
+        const float yv = bld(br, o4, 4 * row(u));
+        const float2 av = bld2(bf, o8, 8 * row(u));
+        const bool in = k0 + u < N;
+        y[u] = in ? yv : 0.f;
+        ai[u] = in ? av : make_float2(-1.f, 1.f);
+    }
+    // Only the chain itself runs while the other waves wait: the values are
+    // complete before the wave starts waiting (the empty asm takes them as
+    // operands), and the loads and stores that need not precede a hand-off
+    // follow it.
+#pragma unroll
+    for (int u = 0; u < LUR; ++u) asm volatile("" ::"v"(y[u]), "v"(ai[u].x), "v"(ai[u].y));
+    // Every wave passes G barriers per sweep; wave q does its part between
+    // its q-th and (q+1)-th (forward) or after the (G-1-q)-th (back).
+    for (int t = 0; t < q; ++t) lds_barrier();
+    {
+        float acc = q ? slot[lane] : 0.f;
+#pragma unroll
+        for (int u = 0; u < LUR; ++u) {
+            acc = (y[u] - ai[u].x * acc) * ai[u].y;
+            y[u] = acc;
+        }
+        slot[lane] = acc;
+    }
+    lds_barrier();
+#pragma unroll
+    for (int u = 0; u < LUR; ++u) {
+        const float cv = bld(bc, o4, 4 * row(u));
+        cc[u] = k0 + u < N - 1 ? cv : k0 + u == N - 1 ? 0.f : -1.f;
+    }
+    for (int t = q + 1; t < G; ++t) lds_barrier();
+    // the slot now holds y_{N-1} = x_{N-1}
+#pragma unroll
+    for (int u = 0; u < LUR; ++u) asm volatile("" ::"v"(cc[u]));
+    for (int t = G - 1; t > q; --t) lds_barrier();
+    {
+        float acc = slot[lane];
+#pragma unroll
+        for (int u = LUR - 1; u >= 0; --u) {
+            acc = y[u] - cc[u] * acc;
+            y[u] = acc;
+        }
+        slot[lane] = acc;
+    }
+    lds_barrier();
+    if (live) {
+#pragma unroll
+        for (int u = 0; u < LUR; ++u)
+            if (k0 + u < N) bst(bx, o4, 4 * row(u), y[u]);
+    }
+    for (int t = q - 1; t >= 0; --t) lds_barrier();
+}
+
+// Workgroups 0 .. ceil(ny/64)-1 take the row systems, the rest the columns.
+__device__ __forceinline__ void luw_solve_body(const SolveArgs &A, int wg, float *slot) {
+    const Dom &d = A.d;
+    const int xw = (d.ny + 63) / 64;
+    if (wg < xw)
+        luw_solve(d.nu, d.ny, wg * 64, reinterpret_cast<const float *>(A.redx),
+                  reinterpret_cast<const float2 *>(A.lux), A.lux + 2 * (size_t)d.nu * d.ny, A.solx, slot);
+    else
+        luw_solve(d.nv, d.nx, (wg - xw) * 64, reinterpret_cast<const float *>(A.redy),
+                  reinterpret_cast<const float2 *>(A.luy), A.luy + 2 * (size_t)d.nv * d.nx, A.soly, slot);
+}
+
 __device__ __forceinline__ void lu_solve_body(const SolveArgs &A, int wave, int lane) {
     const Dom &d = A.d;
     const int xw = (d.ny + 63) / 64;
@@ -862,6 +984,10 @@ __global__ __launch_bounds__(64) void k_lu_factor(SolveArgs A, float *lux, float
     lu_factor_body(A, lux, luy, blockIdx.x, threadIdx.x);
 }
 __global__ __launch_bounds__(64) void k_lu_solve(SolveArgs A) { lu_solve_body(A, blockIdx.x, threadIdx.x); }
+__global__ __launch_bounds__(64 * LUW_MAX) void k_luw_solve(SolveArgs A) {
+    __shared__ float slot[64];
+    luw_solve_body(A, blockIdx.x, slot);
+}
 __global__ __launch_bounds__(64) void k_lu2_factor(SolveArgs A, float *lux, float *luy) {
     lu_factor_body_impl(A, lux, luy, blockIdx.x, threadIdx.x, true);
 }

@@ -321,3 +321,51 @@ def test_tunings_identical_results_and_autotuner(tmp_path):
     for x, y in zip(lu2.state_numpy(), tw.state_numpy()):
         assert np.abs(x - y).max() <= 1e-6 * max(1.0, np.abs(x).max())
     B.close()
+
+
+def test_factored_solve_workgroup_form_and_long_systems():
+    """The factored solve runs systems of up to 512 unknowns as one
+    workgroup per 64 systems (a wave per 32 unknowns, the chain handed from
+    wave to wave), longer ones lane per system.  Every shape must give the
+    Thomas solve's bits: row- and column-dominated domains on both paths,
+    alone and batched (a batch takes the workgroup form only when all its
+    systems fit)."""
+    ws = _ws()
+    shapes = [(1100, 24), (24, 1100), (4096, 20), (20, 4096), (5000, 20), (20, 16384)]
+    lus = []
+    for nx, ny in shapes:
+        w = wl.config2(nx=nx, ny=ny, seed=5)
+        say("case: factored vs Thomas %dx%d" % (nx, ny))
+        th, lu = make(w), make(w)
+        th.set_tuning(16, 128, ws.SOLVE_THOMAS)
+        lu.set_tuning(16, 128, ws.SOLVE_LU)
+        th.advance(12)
+        lu.advance(12)
+        same(th, lu, "factored vs Thomas %dx%d" % (nx, ny))
+        th.close()
+        lus.append((w, lu))
+    small = wl.config2(nx=300, ny=150, seed=11)
+    for members in ((0, 1, 3), (0, 4, 5)):
+        say("case: batched factored solve over %s + 300x150" % ([shapes[m] for m in members],))
+        B = ws.Batch(4)
+        B.set_tuning(16, 128, ws.SOLVE_LU)
+        pairs = []
+        for m in members:
+            w, lu = lus[m]
+            b = make(w)
+            B.attach(b)
+            pairs.append((lu, b))
+        alone = make(small)
+        alone.set_tuning(16, 128, ws.SOLVE_LU)
+        sb = make(small)
+        B.attach(sb)
+        pairs.append((alone, sb))
+        B.advance(12)
+        alone.advance(12)
+        B.sync()
+        for a_, b_ in pairs:
+            same(a_, b_, "batched factored solve, mixed lengths")
+        B.close()
+        for _, b_ in pairs:
+            b_.close()
+        alone.close()
