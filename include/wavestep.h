@@ -104,6 +104,16 @@ typedef struct {
     const double *theta_rad; /* direction from +x, radians                        */
     const double *phase;     /* phase offset, radians                             */
     double ref_depth;        /* m; <= 0: mean depth along the side                */
+    double sponge_reflect;   /* WS_BC_SPONGE: target reflection coefficient R in  *
+                              * [0, 1] of long waves (0: the layer of eq. 30).    *
+                              * The layer's factor becomes gamma^s with           *
+                              * s = min(1, -ln(R) c dt / (4 L ln 2)): a long wave *
+                              * (c = sqrt(g d), d the mean still water depth next *
+                              * to the side) that crosses the layer of width L    *
+                              * and comes back keeps the share R of its amplitude *
+                              * (int_0^L ln gamma = -2 L ln 2).  R = 1 leaves a   *
+                              * solid wall.  The paper names partially reflective *
+                              * sponges without a formula; this is the reading.   */
 } ws_boundary;
 
 /* Fill *g with the defaults above for an nx x ny grid (dx, dy, dt left 0). */

@@ -43,6 +43,7 @@ def lib():
         L.or_destroy.argtypes = [C.c_void_p]
         L.or_set_boundary.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int,
                                       _dp, _dp, _dp, _dp, C.c_double]
+        L.or_set_sponge_reflect.argtypes = [C.c_void_p, C.c_int, C.c_double]
         L.or_set_state.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_double]
         L.or_get_state.argtypes = [C.c_void_p, _dp, _dp, _dp]
         L.or_get_bathy.argtypes = [C.c_void_p, _dp, _dp]
@@ -106,7 +107,7 @@ class Domain:
             self._h = None
 
     def set_boundary(self, side, btype, width=2, amp=(), period=(), theta=(), phase=None,
-                     ref_depth=0.0):
+                     ref_depth=0.0, sponge_reflect=0.0):
         n = len(amp)
         ph = np.zeros(n) if phase is None else phase
         z = np.zeros(1)
@@ -114,6 +115,8 @@ class Domain:
                                    _f64(amp) if n else z, _f64(period) if n else z,
                                    _f64(theta) if n else z, _f64(ph) if n else z,
                                    float(ref_depth))
+        if rc == 0 and btype == SPONGE:
+            rc = lib().or_set_sponge_reflect(self._h, side, float(sponge_reflect))
         if rc:
             raise ValueError("oracle: bad boundary")
 

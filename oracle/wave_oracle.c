@@ -59,6 +59,7 @@ typedef struct {
 
 typedef struct {
     int type, width, ncomp;
+    double expo; /* sponge: exponent s of the damping factor gamma^s (1 = eq. 30) */
     double amp[OR_MAXC], omega[OR_MAXC], k[OR_MAXC], c[OR_MAXC];
     double dirx[OR_MAXC], diry[OR_MAXC], phase[OR_MAXC];
 } or_side;
@@ -547,6 +548,11 @@ double or_sponge_gamma(double dist, double Ls) {
     if (dist >= Ls) return 1.0;
     return 0.5 * (1.0 + cos(M_PI * (Ls - dist) / Ls));
 }
+/* Damping factor of a sponge cell: gamma^s, s = 1 being eq. (30) itself and
+ * s = 0 no damping (see or_set_sponge_reflect). */
+static double sponge_factor(const or_side *s, double gamma) {
+    return s->expo == 1.0 ? gamma : s->expo == 0.0 ? 1.0 : pow(gamma, s->expo);
+}
 static void sponge(const or_domain *D, double *w, double *P, double *Q) {
     const int nx = D->p.nx, ny = D->p.ny;
     const double dx = D->p.dx, dy = D->p.dy;
@@ -556,13 +562,13 @@ static void sponge(const or_domain *D, double *w, double *P, double *Q) {
             if (dstill(D, i, j) <= 0.0) continue;
             double gm = 1.0;
             if (D->side[OR_WEST].type == OR_SPONGE)
-                gm *= or_sponge_gamma((i + 0.5) * dx, D->side[OR_WEST].width * dx);
+                gm *= sponge_factor(&D->side[OR_WEST], or_sponge_gamma((i + 0.5) * dx, D->side[OR_WEST].width * dx));
             if (D->side[OR_EAST].type == OR_SPONGE)
-                gm *= or_sponge_gamma((nx - i - 0.5) * dx, D->side[OR_EAST].width * dx);
+                gm *= sponge_factor(&D->side[OR_EAST], or_sponge_gamma((nx - i - 0.5) * dx, D->side[OR_EAST].width * dx));
             if (D->side[OR_SOUTH].type == OR_SPONGE)
-                gm *= or_sponge_gamma((j + 0.5) * dy, D->side[OR_SOUTH].width * dy);
+                gm *= sponge_factor(&D->side[OR_SOUTH], or_sponge_gamma((j + 0.5) * dy, D->side[OR_SOUTH].width * dy));
             if (D->side[OR_NORTH].type == OR_SPONGE)
-                gm *= or_sponge_gamma((ny - j - 0.5) * dy, D->side[OR_NORTH].width * dy);
+                gm *= sponge_factor(&D->side[OR_NORTH], or_sponge_gamma((ny - j - 0.5) * dy, D->side[OR_NORTH].width * dy));
             if (gm == 1.0) continue;
             size_t c = CI(D, i, j);
             w[c] = D->p.ws + gm * (w[c] - D->p.ws);
@@ -733,6 +739,7 @@ int or_set_boundary(or_domain *D, int side, int type, int width, int ncomp, cons
     or_side *s = &D->side[side];
     s->type = type;
     s->width = width;
+    s->expo = 1.0;
     s->ncomp = type == OR_WAVES ? ncomp : 0;
     fill_bathy_ghosts(D);
     double dref = ref_depth;
@@ -758,6 +765,50 @@ int or_set_boundary(or_domain *D, int side, int type, int width, int ncomp, cons
         s->diry[m] = sin(theta[m]);
         s->phase[m] = phase ? phase[m] : 0.0;
     }
+    return 0;
+}
+
+/* Partially reflective sponge (the paper names such layers without giving a
+ * formula).  The layer multiplies eta, P, Q by gamma^s each step.  A long
+ * wave of speed c = sqrt(g d) that crosses the layer of width L and comes
+ * back spends 2 / (c dt) steps per unit of distance in it, so its amplitude
+ * changes by the factor exp(s (2 / (c dt)) int_0^L ln gamma dD); with
+ * gamma = cos^2(pi (L - D) / (2L)) of eq. (30) the integral is -2 L ln 2, and
+ * the factor exp(-4 s L ln 2 / (c dt)).  A target reflection coefficient R
+ * in (0, 1) thus gives s = -ln(R) c dt / (4 L ln 2), capped at 1 (the layer
+ * of eq. 30 itself, which reflects less than such an R); R = 0 keeps s = 1
+ * and R = 1 gives s = 0, a solid wall.  d: mean still water depth of the
+ * interior cells next to the side, dry cells counting 0 (s = 1 where the
+ * mean is not positive).  The side must be a sponge; set after
+ * or_set_boundary. */
+int or_set_sponge_reflect(or_domain *D, int side, double R) {
+    if (!D || side < 0 || side > 3 || D->side[side].type != OR_SPONGE || !(R >= 0.0 && R <= 1.0)) return -1;
+    or_side *s = &D->side[side];
+    if (R == 0.0) {
+        s->expo = 1.0;
+        return 0;
+    }
+    if (R == 1.0) {
+        s->expo = 0.0;
+        return 0;
+    }
+    double sum = 0.0;
+    int n = 0;
+    if (side == OR_WEST || side == OR_EAST) {
+        int i = side == OR_WEST ? 0 : D->p.nx - 1;
+        for (int j = 0; j < D->p.ny; ++j, ++n) sum += fmax(dstill(D, i, j), 0.0);
+    } else {
+        int j = side == OR_SOUTH ? 0 : D->p.ny - 1;
+        for (int i = 0; i < D->p.nx; ++i, ++n) sum += fmax(dstill(D, i, j), 0.0);
+    }
+    const double d = sum / n;  /* dry cells count as depth 0 */
+    const double L = s->width * (side == OR_WEST || side == OR_EAST ? D->p.dx : D->p.dy);
+    if (!(d > 0.0)) {
+        s->expo = 1.0;
+        return 0;
+    }
+    const double e = -log(R) * sqrt(D->p.g * d) * D->p.dt / (4.0 * L * log(2.0));
+    s->expo = e < 1.0 ? e : 1.0;
     return 0;
 }
 

@@ -60,6 +60,7 @@ struct ws_domain {
     int *health;
     double *scal;                  // small device scratch (reductions)
     int side_type[4], side_width[4], side_ncomp[4];
+    float side_expo[4];   // sponge damping exponent (1 = the layer of eq. 30)
     int cur;
     int64_t step;
     double t;
@@ -176,7 +177,7 @@ static Dom make_dom(const ws_domain *d) {
         m.side[s].type = d->side_type[s];
         m.side[s].width = d->side_width[s];
         m.side[s].ncomp = d->side_ncomp[s];
-        m.side[s].pad = 0;
+        m.side[s].expo = d->side_expo[s];
         m.side[s].tab = d->tab[s];
     }
     return m;
@@ -381,7 +382,7 @@ extern "C" ws_status ws_domain_init(const ws_grid *g, const float *z_corners_dev
     d->pnt = PCR_NT;
     d->solver = WS_SOLVE_PCR;
     d->fstride = L.field;
-    for (int s = 0; s < 4; ++s) { d->side_type[s] = WS_BC_SOLID; d->side_width[s] = 2; }
+    for (int s = 0; s < 4; ++s) { d->side_type[s] = WS_BC_SOLID; d->side_width[s] = 2; d->side_expo[s] = 1.f; }
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipMemsetAsync(d->base, 0, L.total, st);
     if (e == hipSuccess) {
@@ -475,16 +476,30 @@ extern "C" ws_status ws_set_boundary(ws_domain *d, int32_t side, const ws_bounda
     const int nc = b->type == WS_BC_WAVES ? b->n_comp : 0;
     if (nc < 0 || nc > MAXC) return fail(WS_EINVAL, "ws_set_boundary: n_comp %d out of range", b->n_comp);
     if (b->type == WS_BC_SPONGE && b->width_cells < 1) return fail(WS_EINVAL, "ws_set_boundary: sponge width < 1");
+    if (b->type == WS_BC_SPONGE && !(b->sponge_reflect >= 0.0 && b->sponge_reflect <= 1.0))
+        return fail(WS_EINVAL, "ws_set_boundary: sponge_reflect must lie in [0, 1]");
     if (nc > 0 && (!b->amp || !b->period || !b->theta_rad)) return fail(WS_EINVAL, "ws_set_boundary: NULL component array");
     d->side_type[side] = b->type;
     d->side_width[side] = b->width_cells;
     d->side_ncomp[side] = 0;
-    double dref = b->ref_depth;
-    if (nc > 0 && !(dref > 0.0)) {
+    d->side_expo[side] = 1.f;
+    const double R = b->type == WS_BC_SPONGE ? b->sponge_reflect : 0.0;
+    double dref = b->ref_depth, dside = 0.0;
+    if ((nc > 0 && !(dref > 0.0)) || (R > 0.0 && R < 1.0)) {
         Dom m = make_dom(d);
         hipLaunchKernelGGL(k_side_depth, dim3(1), dim3(256), 0, 0, m, side, d->scal);
         HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpy(&dref, d->scal, sizeof(double), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(&dside, d->scal, sizeof(double), hipMemcpyDeviceToHost));
+        if (!(dref > 0.0)) dref = dside;
+    }
+    if (R == 1.0) {
+        d->side_expo[side] = 0.f;  // no damping: a solid wall
+    } else if (R > 0.0 && dside > 0.0) {
+        // partially reflective layer: a long wave crossing it and coming back
+        // keeps the share exp(-4 s L ln 2 / (c dt)) of its amplitude
+        const double L = b->width_cells * (side < 2 ? d->g.dx : d->g.dy);
+        const double e = -std::log(R) * std::sqrt(d->g.g * dside) * d->g.dt / (4.0 * L * std::log(2.0));
+        d->side_expo[side] = (float)(e < 1.0 ? e : 1.0);
     }
     if (nc > 0 && !(dref > 0.0)) return fail(WS_EINVAL, "ws_set_boundary: no positive depth along the side");
     std::vector<double> tab((size_t)MAXC * TABW, 0.0);

@@ -27,7 +27,8 @@ enum { BSNQ = 0, NLSW = 1 };
 enum { FRIC_NONE = 0, FRIC_QUAD = 1, FRIC_MANNING = 2 };
 
 struct SideDev {
-    int type, width, ncomp, pad;
+    int type, width, ncomp;
+    float expo;         // sponge: exponent s of the damping factor gamma^s (1 = eq. 30)
     const double *tab;  // ncomp * TABW
 };
 
@@ -250,6 +251,10 @@ __device__ __forceinline__ void tri_coef(const Dom &d, float dep, float ddep, fl
 
 __device__ __forceinline__ float sponge_gamma(float dist, float Ls) {
     return dist >= Ls ? 1.f : 0.5f * (1.f + cosf(3.14159265358979f * (Ls - dist) / Ls));
+}
+// A partially reflective layer damps by gamma^s (s = 1: the layer of eq. 30).
+__device__ __forceinline__ float sponge_factor(float gamma, float s) {
+    return s == 1.f ? gamma : s == 0.f ? 1.f : powf(gamma, s);
 }
 
 }  // namespace ws

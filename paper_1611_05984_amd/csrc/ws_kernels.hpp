@@ -1120,10 +1120,14 @@ __device__ __forceinline__ void expand_body(const SolveArgs &A, SolveTile &s, in
         }
         if (A.sponge && Dc > 0.f) {
             float gm = 1.f;
-            if (d.side[0].type == BC_SPONGE) gm *= sponge_gamma((i + 0.5f) * d.dx, d.side[0].width * d.dx);
-            if (d.side[1].type == BC_SPONGE) gm *= sponge_gamma((d.nx - i - 0.5f) * d.dx, d.side[1].width * d.dx);
-            if (d.side[2].type == BC_SPONGE) gm *= sponge_gamma((j + 0.5f) * d.dy, d.side[2].width * d.dy);
-            if (d.side[3].type == BC_SPONGE) gm *= sponge_gamma((d.ny - j - 0.5f) * d.dy, d.side[3].width * d.dy);
+            if (d.side[0].type == BC_SPONGE)
+                gm *= sponge_factor(sponge_gamma((i + 0.5f) * d.dx, d.side[0].width * d.dx), d.side[0].expo);
+            if (d.side[1].type == BC_SPONGE)
+                gm *= sponge_factor(sponge_gamma((d.nx - i - 0.5f) * d.dx, d.side[1].width * d.dx), d.side[1].expo);
+            if (d.side[2].type == BC_SPONGE)
+                gm *= sponge_factor(sponge_gamma((j + 0.5f) * d.dy, d.side[2].width * d.dy), d.side[2].expo);
+            if (d.side[3].type == BC_SPONGE)
+                gm *= sponge_factor(sponge_gamma((d.ny - j - 0.5f) * d.dy, d.side[3].width * d.dy), d.side[3].expo);
             if (gm != 1.f) {
                 e *= gm;
                 P *= gm;

@@ -40,7 +40,8 @@ class Boundary(C.Structure):
     _fields_ = [("type", C.c_int32), ("width_cells", C.c_int32), ("n_comp", C.c_int32),
                 ("reserved", C.c_int32), ("amp", C.POINTER(C.c_double)),
                 ("period", C.POINTER(C.c_double)), ("theta_rad", C.POINTER(C.c_double)),
-                ("phase", C.POINTER(C.c_double)), ("ref_depth", C.c_double)]
+                ("phase", C.POINTER(C.c_double)), ("ref_depth", C.c_double),
+                ("sponge_reflect", C.c_double)]
 
 
 class Tuning(C.Structure):
@@ -174,12 +175,12 @@ class Domain:
             pass
 
     def set_boundary(self, side, kind, width=2, amp=(), period=(), theta=(), phase=None,
-                     ref_depth=0.0):
+                     ref_depth=0.0, sponge_reflect=0.0):
         n = len(amp)
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in
                 (amp, period, theta, phase if phase is not None else np.zeros(n))]
         ptrs = [a.ctypes.data_as(C.POINTER(C.c_double)) for a in arrs]
-        b = Boundary(int(kind), int(width), n, 0, *ptrs, float(ref_depth))
+        b = Boundary(int(kind), int(width), n, 0, *ptrs, float(ref_depth), float(sponge_reflect))
         _check(lib().ws_set_boundary(self._h, int(side), C.byref(b)), "ws_set_boundary")
 
     def set_state(self, w, P, Q, t=0.0, stream=None):

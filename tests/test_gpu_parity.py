@@ -125,6 +125,34 @@ def test_mixed_boundaries_ragged_tiles(nx, ny):
     assert np.all(ge >= b.astype(np.float32) - 1e-6)
 
 
+def test_partially_reflective_sponge_parity():
+    """Partially reflective sponges (target reflection 0.5 north, 0.2
+    south, beside the oblique wave maker and the beach of the mixed case)
+    match the oracle; R = 1 leaves the GPU state equal to a solid wall's, bit
+    for bit."""
+    ws = _ws()
+    w = _mixed_case(150, 70)
+    gpu, ora = build_pair(w)
+    for d in (gpu, ora):
+        d.set_boundary(wl.NORTH, wl.SPONGE, 12, sponge_reflect=0.5)
+        d.set_boundary(wl.SOUTH, wl.SPONGE, 8, sponge_reflect=0.2)
+    say("case: partially reflective sponges 150x70")
+    gpu.advance(200)
+    ora.advance(200)
+    check(gpu, ora, 0.03, 0.5, rel=1e-4, what="step 200")
+    w2 = _mixed_case(96, 40, seed=5)
+    a, _ = build_pair(w2)
+    b, _ = build_pair(w2)
+    a.set_boundary(wl.SOUTH, wl.SPONGE, 8, sponge_reflect=1.0)
+    b.set_boundary(wl.SOUTH, wl.SOLID)
+    a.advance(60)
+    b.advance(60)
+    for x, y in zip(a.state_numpy(), b.state_numpy()):
+        assert np.array_equal(x, y)
+    with pytest.raises(ws.WaveStepError):
+        a.set_boundary(wl.EAST, wl.SPONGE, 8, sponge_reflect=-0.1)
+
+
 @pytest.mark.parametrize("params", [dict(model=1), dict(friction=1, friction_coef=0.01),
                                     dict(friction=2, friction_coef=0.02),
                                     dict(n_corr=1), dict(n_corr=3, fstar_extrap=2),

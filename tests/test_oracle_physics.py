@@ -295,6 +295,41 @@ def test_sponge_absorbs_compared_to_wall():
     assert res[1] < 0.05 * res[0], res
 
 
+def test_partially_reflective_sponge():
+    """A sponge given a target reflection coefficient R damps by gamma^s with
+    s = -ln(R) c dt / (4 L ln 2) (gamma of eq. 30): a long wave crossing the
+    layer and coming back keeps exp(s (2 / (c dt)) int_0^L ln gamma) = R of its
+    amplitude.  A solitary wave (H/d = 0.05) sent into the layer must come
+    back with R of the height a wall returns, to 0.02; R = 0 is the sponge of
+    eq. 30 and R = 1 a solid wall, bit for bit."""
+    nx, ny, dx = 300, 2, 0.1
+    dt = wl.courant_dt(0.2, dx, 1.0)
+
+    def run(east, r=None):
+        D = o.Domain(nx, ny, dx, dx, dt, -np.ones((ny + 1, nx + 1)))
+        if r is None:
+            D.set_boundary(o.EAST, east, 60)
+        else:
+            D.set_boundary(o.EAST, east, 60, sponge_reflect=r)
+        D.add_solitary(0.05, 0.0, 12.0, 0.1)
+        D.advance(1500)            # the reflected pulse is back in x < 20 m
+        return D.state()
+
+    wall, sponge = run(o.SOLID), run(o.SPONGE)
+    aw = np.abs(wall[0][:, :200]).max()
+    rs = (0.0, 0.25, 0.5, 0.75, 1.0)
+    out = [run(o.SPONGE, r) for r in rs]
+    assert all(np.array_equal(a, b) for a, b in zip(out[0], sponge))
+    assert all(np.array_equal(a, b) for a, b in zip(out[-1], wall))
+    ratio = [float(np.abs(st[0][:, :200]).max() / aw) for st in out]
+    assert ratio[0] < 0.05, ratio
+    for r, m in zip(rs[1:-1], ratio[1:-1]):
+        assert abs(m - r) <= 0.02, (r, m)
+    with pytest.raises(ValueError):
+        D = o.Domain(nx, ny, dx, dx, dt, -np.ones((ny + 1, nx + 1)))
+        D.set_boundary(o.EAST, o.SPONGE, 60, sponge_reflect=1.5)
+
+
 # ------------------------------------------------------------ integrator
 @pytest.mark.slow
 def test_predictor_corrector_converges_in_time():
