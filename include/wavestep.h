@@ -238,6 +238,25 @@ ws_status ws_batch_sync(ws_batch *b, void *stream);
  * batch has advanced since. */
 ws_status ws_batch_status(ws_batch *b, int32_t slot, int64_t *step, double *t, int32_t *health);
 
+/* ---- Corrector iteration until convergence (sec. 2.3: the corrector is
+ * iterated a set number of times or until the variables converge).
+ * With tol_w > 0, every full step of ws_advance iterates the corrector until
+ * the largest change over the interior cells between two successive
+ * iterates (the predictor's being the first) is at most tol_w for w (m) and
+ * at most tol_pq for P and Q (m^2/s), or until n_corr correctors have run
+ * (the grid's n_corr is the cap; the Euler start-up steps run none).  The
+ * sponge follows the last corrector as always.  Each test is a device
+ * reduction and an 8-byte read-back, so ws_advance synchronizes its stream
+ * once per corrector in this mode.  tol_w <= 0 restores the fixed count (the
+ * default).  Resets the counters of ws_corrector_stats.  WS_EBUSY for a
+ * domain attached to a batch; ws_batch_attach refuses (WS_EINVAL) a domain
+ * in this mode. */
+ws_status ws_set_corrector_tolerance(ws_domain *d, double tol_w, double tol_pq);
+/* Correctors the last step ran and the total since the tolerance was set;
+ * the changes of w and of P, Q measured after the last corrector (tolerance
+ * mode only; any pointer may be NULL).  Host only. */
+ws_status ws_corrector_stats(const ws_domain *d, int32_t *last, int64_t *total, double *dw, double *dpq);
+
 /* ---- Tuning: launch shapes chosen per grid shape.
  * stencil_rows: rows each stencil workgroup streams (8, 16, 24, 32, 48 or
  * 64; taller strips repeat fewer warm-up rows, shorter ones give more

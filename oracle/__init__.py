@@ -44,6 +44,10 @@ def lib():
         L.or_set_boundary.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int,
                                       _dp, _dp, _dp, _dp, C.c_double]
         L.or_set_sponge_reflect.argtypes = [C.c_void_p, C.c_int, C.c_double]
+        L.or_set_corrector_tolerance.argtypes = [C.c_void_p, C.c_double, C.c_double]
+        L.or_set_n_corr.argtypes = [C.c_void_p, C.c_int]
+        L.or_corrector_stats.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int64),
+                                         _dp, _dp]
         L.or_set_state.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_double]
         L.or_get_state.argtypes = [C.c_void_p, _dp, _dp, _dp]
         L.or_get_bathy.argtypes = [C.c_void_p, _dp, _dp]
@@ -119,6 +123,26 @@ class Domain:
             rc = lib().or_set_sponge_reflect(self._h, side, float(sponge_reflect))
         if rc:
             raise ValueError("oracle: bad boundary")
+
+    def set_corrector_tolerance(self, tol_w, tol_pq):
+        """Iterate the corrector until the largest change of w is within
+        tol_w and that of P, Q within tol_pq (at most n_corr times); tol_w
+        <= 0: the fixed count."""
+        if lib().or_set_corrector_tolerance(self._h, float(tol_w), float(tol_pq)):
+            raise ValueError("oracle: bad tolerance")
+
+    def set_n_corr(self, n_corr):
+        """Corrector count of the following steps (the cap in tolerance mode)."""
+        if lib().or_set_n_corr(self._h, int(n_corr)):
+            raise ValueError("oracle: bad corrector count")
+
+    def corrector_stats(self):
+        """(correctors of the last step, total since the tolerance was set,
+        change of w and of P, Q after the last corrector)."""
+        last, total = C.c_int(0), C.c_int64(0)
+        dw, dpq = np.zeros(1), np.zeros(1)
+        lib().or_corrector_stats(self._h, C.byref(last), C.byref(total), _f64(dw), _f64(dpq))
+        return last.value, total.value, float(dw[0]), float(dpq[0])
 
     def set_state(self, w, P, Q, t=0.0):
         n = self.nx * self.ny

@@ -75,6 +75,11 @@ typedef struct {
     int64_t step;      /* number of completed time steps since the last start */
     double t;
     int health;        /* 0 ok, 1 non-finite state seen */
+    /* corrector iteration until convergence (sec. 2.3): off while tol_w <= 0 */
+    double tol_w, tol_pq;     /* largest allowed change of w, of P and Q       */
+    int last_corr;            /* correctors the last step ran                  */
+    int64_t total_corr;       /* correctors run since the tolerance was set    */
+    double last_dw, last_dpq; /* changes measured after the last corrector     */
 } or_domain;
 
 /* ---------------------------------------------------------------- indexing */
@@ -655,8 +660,24 @@ static void step_once(or_domain *D) {
     solve_cols(D, V1, Q1, t1);
     dry_fix_pq(D, w1, P1, Q1);
 
+    /* with a tolerance set, the corrector is iterated until the largest
+     * change of w and that of P, Q between two successive iterates (the
+     * predictor's for the first) fall within it, at most n_corr times */
+    const int conv = D->tol_w > 0.0;
+    double *wp = NULL, *Pp = NULL, *Qp = NULL;
+    if (conv) {
+        wp = calloc(N, sizeof(double));
+        Pp = calloc(N, sizeof(double));
+        Qp = calloc(N, sizeof(double));
+    }
+    int ncorr = 0;
     if (!euler)
         for (int k = 0; k < D->p.n_corr; ++k) {
+            if (conv) {
+                memcpy(wp, w1, N * sizeof(double));
+                memcpy(Pp, P1, N * sizeof(double));
+                memcpy(Qp, Q1, N * sizeof(double));
+            }
             fill_ghosts(D, w1, P1, Q1, t1);
             rhs(D, w1, P1, Q1, Ek, Fk, Gk, Fsk, Gsk);
 #pragma omp parallel for schedule(static)
@@ -673,7 +694,25 @@ static void step_once(or_domain *D) {
             solve_rows(D, U1, P1, t1);
             solve_cols(D, V1, Q1, t1);
             dry_fix_pq(D, w1, P1, Q1);
+            ++ncorr;
+            if (conv) {
+                double dw = 0.0, dpq = 0.0;
+                for (int j = 0; j < D->p.ny; ++j)
+                    for (int i = 0; i < D->p.nx; ++i) {
+                        size_t c = CI(D, i, j);
+                        const double a = fabs(w1[c] - wp[c]);
+                        const double b = fmax(fabs(P1[c] - Pp[c]), fabs(Q1[c] - Qp[c]));
+                        dw = (a > dw || a != a) ? a : dw;       /* a NaN change never converges */
+                        dpq = (b > dpq || b != b) ? b : dpq;
+                    }
+                D->last_dw = dw;
+                D->last_dpq = dpq;
+                if (dw <= D->tol_w && dpq <= D->tol_pq) break;
+            }
         }
+    D->last_corr = ncorr;
+    D->total_corr += ncorr;
+    free(wp); free(Pp); free(Qp);
 
     sponge(D, w1, P1, Q1);
     memcpy(D->w, w1, N * sizeof(double));
@@ -765,6 +804,41 @@ int or_set_boundary(or_domain *D, int side, int type, int width, int ncomp, cons
         s->diry[m] = sin(theta[m]);
         s->phase[m] = phase ? phase[m] : 0.0;
     }
+    return 0;
+}
+
+/* Corrector iteration until convergence (sec. 2.3): with tol_w > 0 every
+ * full step iterates the corrector until max |w_k - w_{k-1}| <= tol_w and
+ * max(|P_k - P_{k-1}|, |Q_k - Q_{k-1}|) <= tol_pq over the interior cells
+ * (iterate 0 being the predictor's), at most n_corr times; the sponge
+ * follows as always.  tol_w <= 0 restores the fixed count.  Resets the
+ * counters of or_corrector_stats. */
+int or_set_corrector_tolerance(or_domain *D, double tol_w, double tol_pq) {
+    if (!D || tol_w != tol_w || tol_pq != tol_pq) return -1;
+    D->tol_w = tol_w;
+    D->tol_pq = tol_pq;
+    D->last_corr = 0;
+    D->total_corr = 0;
+    D->last_dw = D->last_dpq = 0.0;
+    return 0;
+}
+
+/* Corrector count of the following steps (fixed-count mode; the cap in the
+ * tolerance mode). */
+int or_set_n_corr(or_domain *D, int n_corr) {
+    if (!D || n_corr < 0) return -1;
+    D->p.n_corr = n_corr;
+    return 0;
+}
+
+/* Correctors of the last step and since the tolerance was set; the changes
+ * measured after the last corrector (tolerance mode only). */
+int or_corrector_stats(const or_domain *D, int *last, int64_t *total, double *dw, double *dpq) {
+    if (!D) return -1;
+    if (last) *last = D->last_corr;
+    if (total) *total = D->total_corr;
+    if (dw) *dw = D->last_dw;
+    if (dpq) *dpq = D->last_dpq;
     return 0;
 }
 

@@ -77,6 +77,10 @@ struct ws_domain {
     StencilArgs *vsa;              // pass argument tables (device), batch use only
     SolveArgs *vso;
     int nvar;
+    double tol_w, tol_pq;          // corrector iteration until convergence: off while tol_w <= 0
+    int last_corr;                 // correctors the last step ran
+    int64_t total_corr;            // correctors since the tolerance was set
+    double last_dw, last_dpq;      // changes measured after the last corrector
 };
 
 static ws_status busy_check(const ws_domain *d, const char *who) {
@@ -331,6 +335,64 @@ __global__ void k_side_depth(Dom d, int side, double *out) {
 }
 
 static dim3 cells_grid(int nx, int ny) { return dim3((nx + 255) / 256, ny); }
+
+// Largest change between two iterates of the state over the interior cells:
+// res[0] = max |eta1 - eta0|, res[1] = max(|P1 - P0|, |Q1 - Q0|), kept as
+// float bits (non-negative floats order as unsigned integers); a non-finite
+// change counts as +inf.
+__device__ __forceinline__ float change(float a, float b) {
+    const float c = fabsf(a - b);
+    return isfinite(c) ? c : INFINITY;
+}
+__global__ void k_residual(Dom d, const float *e0, const float *p0, const float *q0, const float *e1, const float *p1,
+                           const float *q1, unsigned *res) {
+    float mw = 0.f, mq = 0.f;
+    const int n = d.nx * d.ny;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+        const int j = k / d.nx, i = k - j * d.nx;
+        const size_t o = (size_t)j * d.pitch + i;
+        mw = fmaxf(mw, change(e1[o], e0[o]));
+        mq = fmaxf(mq, fmaxf(change(p1[o], p0[o]), change(q1[o], q0[o])));
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        mw = fmaxf(mw, __shfl_xor(mw, off));
+        mq = fmaxf(mq, __shfl_xor(mq, off));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&res[0], __float_as_uint(mw));
+        atomicMax(&res[1], __float_as_uint(mq));
+    }
+}
+__global__ void k_zero_words(unsigned *p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
+// The sponge of the step's end as a pass of its own (the same arithmetic as
+// the last expand's epilogue, which applies it when the corrector count is
+// fixed): eta, P, Q times the layers' factors where the still water depth is
+// positive.
+__global__ void k_sponge(Dom d, float *e, float *P, float *Q) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i >= d.nx || j >= d.ny) return;
+    const float *r0 = d.D + (size_t)j * d.zpitch, *r1 = r0 + d.zpitch;
+    const float Dc = 0.25f * ((r0[i] + r0[i + 1]) + (r1[i] + r1[i + 1]));
+    if (!(Dc > 0.f)) return;
+    float gm = 1.f;
+    if (d.side[0].type == BC_SPONGE)
+        gm *= sponge_factor(sponge_gamma((i + 0.5f) * d.dx, d.side[0].width * d.dx), d.side[0].expo);
+    if (d.side[1].type == BC_SPONGE)
+        gm *= sponge_factor(sponge_gamma((d.nx - i - 0.5f) * d.dx, d.side[1].width * d.dx), d.side[1].expo);
+    if (d.side[2].type == BC_SPONGE)
+        gm *= sponge_factor(sponge_gamma((j + 0.5f) * d.dy, d.side[2].width * d.dy), d.side[2].expo);
+    if (d.side[3].type == BC_SPONGE)
+        gm *= sponge_factor(sponge_gamma((d.ny - j - 0.5f) * d.dy, d.side[3].width * d.dy), d.side[3].expo);
+    if (gm != 1.f) {
+        const size_t o = (size_t)j * d.pitch + i;
+        e[o] *= gm;
+        P[o] *= gm;
+        Q[o] *= gm;
+    }
+}
 
 // ------------------------------------------------------------------ API
 extern "C" ws_status ws_domain_init(const ws_grid *g, const float *z_corners_dev, void *workspace_dev,
@@ -907,10 +969,14 @@ extern "C" ws_status ws_advance(ws_domain *d, int64_t nsteps, void *stream) {
     }
     const Dom m = make_dom(d);
     const bool makers = has_makers(d);
+    const bool conv = d->tol_w > 0.0;
+    bool sponges = false;
+    for (int q = 0; q < 4; ++q) sponges = sponges || d->side_type[q] == WS_BC_SPONGE;
+    unsigned *dres = reinterpret_cast<unsigned *>(reinterpret_cast<char *>(d->health) + 128);
     for (int64_t n = 0; n < nsteps; ++n) {
         const int64_t s = d->step + 1;
         const bool euler = s <= 2;
-        const int K = euler ? 0 : d->g.n_corr;
+        int K = euler ? 0 : d->g.n_corr;
         const double t0 = d->t, t1 = d->t + d->g.dt;
         if (makers) {
             const int n = 8 * d->gl * GHL;
@@ -921,11 +987,40 @@ extern "C" ws_status ws_advance(ws_domain *d, int64_t nsteps, void *stream) {
         SolveArgs so;
         for (int p = 0; p <= K; ++p) {
             pass_args(d, m, euler, d->cur, (int)(s % 3), p, sa, so);
+            if (conv) so.sponge = 0;  // applied once the count is known
             ws_status r = run_pass(d, sa, so, st);
             if (r != WS_OK) return r;
+            if (conv && p >= 1) {
+                // change against the previous iterate (the pass's input state)
+                const int a = d->cur, b1 = (a + 1) % 3, c1 = (a + 2) % 3;
+                const int in = (p & 1) ? b1 : c1, out = (p & 1) ? c1 : b1;
+                hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, st, dres, 2);
+                const int nb = std::min(1024, (d->g.nx * d->g.ny + 255) / 256);
+                hipLaunchKernelGGL(k_residual, dim3(nb), dim3(256), 0, st, m, d->st[in][0], d->st[in][1],
+                                   d->st[in][2], d->st[out][0], d->st[out][1], d->st[out][2], dres);
+                unsigned h[2] = {0u, 0u};
+                HIPCHK(hipMemcpyAsync(h, dres, sizeof h, hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+                float fw, fq;
+                std::memcpy(&fw, &h[0], 4);
+                std::memcpy(&fq, &h[1], 4);
+                d->last_dw = fw;
+                d->last_dpq = fq;
+                if (fw <= d->tol_w && fq <= d->tol_pq) {
+                    K = p;
+                    break;
+                }
+            }
         }
         const int b = (d->cur + 1) % 3, c = (d->cur + 2) % 3;
         d->cur = K == 0 ? b : ((K & 1) ? c : b);
+        if (conv) {
+            if (sponges)
+                hipLaunchKernelGGL(k_sponge, cells_grid(d->g.nx, d->g.ny), dim3(256), 0, st, m, d->st[d->cur][0],
+                                   d->st[d->cur][1], d->st[d->cur][2]);
+            d->last_corr = K;
+            d->total_corr += K;
+        }
         d->step = s;
         d->t = t1;
     }
@@ -943,6 +1038,26 @@ extern "C" ws_status ws_query(ws_domain *d, void *stream, int64_t *step, double 
     if (t) *t = d->t;
     if (health) *health = h;
     if (h) return fail(WS_ENONFINITE, "ws_query: non-finite state");
+    return WS_OK;
+}
+
+extern "C" ws_status ws_set_corrector_tolerance(ws_domain *d, double tol_w, double tol_pq) {
+    if (!d || tol_w != tol_w || tol_pq != tol_pq) return fail(WS_EINVAL, "ws_set_corrector_tolerance: bad argument");
+    if (d->batch) return fail(WS_EBUSY, "ws_set_corrector_tolerance: domain is attached to a batch");
+    d->tol_w = tol_w;
+    d->tol_pq = tol_pq;
+    d->last_corr = 0;
+    d->total_corr = 0;
+    d->last_dw = d->last_dpq = 0.0;
+    return WS_OK;
+}
+
+extern "C" ws_status ws_corrector_stats(const ws_domain *d, int32_t *last, int64_t *total, double *dw, double *dpq) {
+    if (!d) return fail(WS_EINVAL, "ws_corrector_stats: NULL domain");
+    if (last) *last = d->last_corr;
+    if (total) *total = d->total_corr;
+    if (dw) *dw = d->last_dw;
+    if (dpq) *dpq = d->last_dpq;
     return WS_OK;
 }
 
@@ -1182,6 +1297,8 @@ extern "C" ws_status ws_batch_destroy(ws_batch *b) {
 extern "C" ws_status ws_batch_attach(ws_batch *b, ws_domain *d, int32_t *slot) {
     if (!b || !d) return fail(WS_EINVAL, "ws_batch_attach: bad argument");
     if (d->batch) return fail(WS_EBUSY, "ws_batch_attach: domain already attached");
+    if (d->tol_w > 0.0)
+        return fail(WS_EINVAL, "ws_batch_attach: the corrector tolerance mode is single-domain only");
     // no sync: the tables are rebuilt (after a pull) by the next ws_batch_advance
     for (int sl = 0; sl < b->max; ++sl)
         if (!b->slots[sl]) {

@@ -99,6 +99,9 @@ def lib():
             "ws_batch_set_stop": (C.c_int, [vp, i32, i64]),
             "ws_batch_status": (C.c_int, [vp, i32, C.POINTER(i64), C.POINTER(f64), C.POINTER(i32)]),
             "ws_batch_sync": (C.c_int, [vp, vp]),
+            "ws_set_corrector_tolerance": (C.c_int, [vp, f64, f64]),
+            "ws_corrector_stats": (C.c_int, [vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(f64),
+                                             C.POINTER(f64)]),
         }
         for name, (res, args) in sigs.items():
             fn = getattr(L, name)
@@ -218,6 +221,21 @@ class Domain:
         if st not in (OK, ENOTDD):
             _check(st, "ws_apply_edit")
         return st
+
+    def set_corrector_tolerance(self, tol_w, tol_pq):
+        """Iterate the corrector until the largest change of w is within
+        tol_w (m) and that of P, Q within tol_pq (m^2/s), at most n_corr
+        times; tol_w <= 0 restores the fixed count."""
+        _check(lib().ws_set_corrector_tolerance(self._h, float(tol_w), float(tol_pq)),
+               "ws_set_corrector_tolerance")
+
+    def corrector_stats(self):
+        """(correctors of the last step, total since the tolerance was set,
+        change of w and of P, Q after the last corrector)."""
+        last, total, dw, dpq = C.c_int32(0), C.c_int64(0), C.c_double(0), C.c_double(0)
+        _check(lib().ws_corrector_stats(self._h, C.byref(last), C.byref(total), C.byref(dw),
+                                        C.byref(dpq)), "ws_corrector_stats")
+        return last.value, total.value, dw.value, dpq.value
 
     def query(self, stream=None):
         step, t, health = C.c_int64(), C.c_double(), C.c_int32()

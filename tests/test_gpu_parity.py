@@ -153,6 +153,53 @@ def test_partially_reflective_sponge_parity():
         a.set_boundary(wl.EAST, wl.SPONGE, 8, sponge_reflect=-0.1)
 
 
+def test_corrector_tolerance_mode():
+    """Corrector iteration until convergence on the GPU: a tolerance no
+    change exceeds stops after one corrector and one no change meets runs the
+    cap, equal bit for bit to the fixed-count runs (sponge and wave maker
+    included); in between, the per-step counts vary, every step that stopped
+    early reports changes within the tolerance, and the oracle stepped with
+    the same counts matches the state.  Batches refuse the mode."""
+    ws = _ws()
+    w = _mixed_case(96, 40, seed=5)
+    say("case: corrector tolerance mode 96x40")
+    fixed1, _ = build_pair(w, n_corr=1)
+    loose, _ = build_pair(w, n_corr=4)
+    loose.set_corrector_tolerance(1e9, 1e9)
+    fixed3, _ = build_pair(w, n_corr=3)
+    tight, _ = build_pair(w, n_corr=3)
+    tight.set_corrector_tolerance(1e-30, 1e-30)
+    for d in (fixed1, loose, fixed3, tight):
+        d.advance(40)
+    for a, b in ((fixed1, loose), (fixed3, tight)):
+        for x, y in zip(a.state_numpy(), b.state_numpy()):
+            assert np.array_equal(x, y)
+    assert loose.corrector_stats()[:2] == (1, 38) and tight.corrector_stats()[:2] == (3, 114)
+    tol_w, tol_pq = 2e-5, 3e-4
+    gpu, ora = build_pair(w, n_corr=4)
+    gpu.set_corrector_tolerance(tol_w, tol_pq)
+    counts = []
+    for n in range(80):
+        gpu.advance(1)
+        last, _, dw, dpq = gpu.corrector_stats()
+        counts.append(last)
+        if 0 < last < 4:
+            assert dw <= tol_w and dpq <= tol_pq, (n, last, dw, dpq)
+        ora.set_n_corr(max(last, 0))
+        ora.advance(1)
+    say("  counts %s" % counts)
+    assert counts[:2] == [0, 0] and len(set(counts[2:])) > 1, counts
+    check(gpu, ora, 0.03, 0.5, rel=1e-4, what="tolerance mode, step 80")
+    B = ws.Batch(2)
+    with pytest.raises(ws.WaveStepError):
+        B.attach(gpu)
+    gpu.set_corrector_tolerance(0.0, 0.0)
+    B.attach(gpu)
+    with pytest.raises(ws.WaveStepError):
+        gpu.set_corrector_tolerance(1e-5, 1e-5)
+    B.close()
+
+
 @pytest.mark.parametrize("params", [dict(model=1), dict(friction=1, friction_coef=0.01),
                                     dict(friction=2, friction_coef=0.02),
                                     dict(n_corr=1), dict(n_corr=3, fstar_extrap=2),

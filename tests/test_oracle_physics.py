@@ -330,6 +330,49 @@ def test_partially_reflective_sponge():
         D.set_boundary(o.EAST, o.SPONGE, 60, sponge_reflect=1.5)
 
 
+def _conv_case(n_corr, tol=None):
+    w = wl.config2(nx=120, ny=30, seed=4)
+    D = make(w, n_corr=n_corr)
+    if tol is not None:
+        D.set_corrector_tolerance(*tol)
+    return D
+
+
+def test_corrector_iterated_to_a_tolerance():
+    """Corrector iteration until convergence (sec. 2.3).  A tolerance no
+    change can exceed stops after one corrector and one no change can meet
+    runs the cap: both equal the fixed-count runs bit for bit.  The change
+    between successive iterates shrinks with every corrector (the AM4
+    corrector is a contraction at this time step), so a tolerance between
+    two of those changes stops in between, with the last change within it."""
+    steps = 40
+    one = _conv_case(1)
+    one.advance(steps)
+    loose = _conv_case(4, (1e9, 1e9))
+    loose.advance(steps)
+    assert all(np.array_equal(a, b) for a, b in zip(one.state(), loose.state()))
+    assert loose.corrector_stats()[:2] == (1, steps - 2)
+    three = _conv_case(3)
+    three.advance(steps)
+    tight = _conv_case(3, (1e-300, 1e-300))
+    tight.advance(steps)
+    assert all(np.array_equal(a, b) for a, b in zip(three.state(), tight.state()))
+    assert tight.corrector_stats()[:2] == (3, 3 * (steps - 2))
+    # change after k correctors, same history each time
+    ch = []
+    for k in range(1, 6):
+        D = _conv_case(k, (1e-300, 1e-300))
+        D.advance(steps)
+        ch.append(D.corrector_stats()[2:])
+    for (w0, q0), (w1, q1) in zip(ch, ch[1:]):
+        assert w1 < w0 and q1 < q0, ch
+    tw, tq = np.sqrt(ch[1][0] * ch[2][0]), np.sqrt(ch[1][1] * ch[2][1])
+    D = _conv_case(5, (tw, tq))
+    D.advance(steps)
+    last, total, dw, dpq = D.corrector_stats()
+    assert last == 3 and dw <= tw and dpq <= tq, (last, dw, dpq, ch)
+
+
 # ------------------------------------------------------------ integrator
 @pytest.mark.slow
 def test_predictor_corrector_converges_in_time():
