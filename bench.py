@@ -174,15 +174,16 @@ def serving(args):
 
 
 def k_variants(args, torch, ws, wl):
-    """Rates of the big-domain workload with K = 0 and K = 1 correctors."""
+    """Rates of the big-domain workload with K = 0 and K = 1 correctors, and
+    in the NLSW model (K = 2; no dispersion, so no tridiagonal solves)."""
     w = wl.config3(n=args.n)
     out = {}
-    for K in (0, 1):
-        d = _make(ws, w, n_corr=K)
+    for key, params in (("K0", dict(n_corr=0)), ("K1", dict(n_corr=1)), ("nlsw_K2", dict(model=ws.NLSW))):
+        d = _make(ws, w, **params)
         d.advance(5)
         n = max(10, args.steps // 4)
         t = _timed(torch, lambda k: d.advance(k), n)
-        out["K%d" % K] = w.nx * w.ny * n / t
+        out[key] = w.nx * w.ny * n / t
         d.close()
         del d
         torch.cuda.empty_cache()

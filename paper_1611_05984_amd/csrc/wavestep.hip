@@ -881,6 +881,7 @@ static void pass_args(const ws_domain *d, const Dom &m, bool euler, int cur, int
     so.luy = d->luy;
     so.layout = (d->solver == WS_SOLVE_LU || d->solver == WS_SOLVE_LU2) ? 1 : 0;
     so.sponge = p == K ? 1 : 0;
+    so.nlsw = g.model == WS_NLSW ? 1 : 0;
 }
 
 static bool has_makers(const ws_domain *d) {
@@ -943,13 +944,15 @@ static ws_status run_pass(ws_domain *d, const StencilArgs &sa, const SolveArgs &
         ProfScope p(d, st, sa.kind == 2 ? WS_K_CORRECTOR : WS_K_PREDICTOR);
         launch_stencil(d->sy, strips(d), st, sa);
     }
-    {
-        ProfScope p(d, st, WS_K_REDUCE);
-        hipLaunchKernelGGL(k_reduce, tiles(d), dim3(NT), 0, st, so);
-    }
-    {
-        ProfScope p(d, st, WS_K_SOLVE);
-        launch_reduced(d, st, so);
+    if (!so.nlsw) {  // NLSW: identity systems, nothing to solve
+        {
+            ProfScope p(d, st, WS_K_REDUCE);
+            hipLaunchKernelGGL(k_reduce, tiles(d), dim3(NT), 0, st, so);
+        }
+        {
+            ProfScope p(d, st, WS_K_SOLVE);
+            launch_reduced(d, st, so);
+        }
     }
     {
         ProfScope p(d, st, WS_K_EXPAND);

@@ -348,6 +348,7 @@ struct SolveArgs {
     const float *gh0, *gh1;    // wave-maker ghosts at t^n and t^{n+1}
     int *health;
     int sponge;
+    int nlsw;  // NLSW: the systems are the identity, the increments in rx, ry are final
 };
 
 constexpr int TXP = TX + 1;  // padded LDS row: segment k of row r starts at bank r + 16k
@@ -1068,7 +1069,10 @@ __device__ __forceinline__ void expand_body(const SolveArgs &A, SolveTile &s, in
         pre_q[m] = in ? A.qbase[o] : 0.f;
     }
     stage_tile(A, s, i0, j0);
-    if (tid < 64) {
+    if (A.nlsw) {
+        // identity systems (eq. 21-22 with the dispersive coefficients zero):
+        // the partitioned solve would return the increments unchanged
+    } else if (tid < 64) {
         const int row = tid % 16, seg = tid / 16, k0 = seg * MX;
         const int k = 2 * (bx * (TX / MX) + seg), j = j0 + row;
         float x0 = 0.f, xl = 0.f;
