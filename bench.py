@@ -156,7 +156,8 @@ def batched_vs_plain(args, torch, ws, wl):
             "batched_over_plain_graph": (cells * n / t_b) / (cells * 3 * reps / t_g),
             "batched_over_plain_eager": (cells * n / t_b) / (cells * n / t_p),
             "unit": "cell-updates/s", "healthy": all(h == 0 for h in health),
-            "batch_tuning": {"stencil_rows": tuning[0], "pcr_threads": tuning[1],
+            "batch_tuning": {"stencil_rows": tuning[0], "corrector_rows": tuning[3] or tuning[0],
+                             "pcr_threads": tuning[1],
                              "solver": ("pcr", "thomas", "lu", "lu2")[tuning[2]]}}
 
 
@@ -193,7 +194,7 @@ def k_variants(args, torch, ws, wl):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU; --gpus %d is not supported "
+        print("bench.py: measures one GPU only; --gpus %d is not supported "
               "(the multi-GPU decomposition is design-only)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import numpy as np
@@ -290,7 +291,8 @@ def main():
         "data": "synthetic (seeded shelf bathymetry + fractal noise, JONSWAP maker)",
         "config": {"workload": w.name + "_jonswap64_sponge64", "nx": w.nx, "ny": w.ny,
                    "dx_m": w.dx, "dt_s": w.dt, "n_corr": 2, "fstar_extrap": 1,
-                   "tuning": {"stencil_rows": tuning[0], "pcr_threads": tuning[1],
+                   "tuning": {"stencil_rows": tuning[0], "corrector_rows": tuning[3] or tuning[0],
+                              "pcr_threads": tuning[1],
                               "solver": ("pcr", "thomas", "lu", "lu2")[tuning[2]]},
                    "boundaries": "W waves(64 comps) / E sponge(64) / N,S walls"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

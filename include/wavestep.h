@@ -260,15 +260,22 @@ ws_status ws_corrector_stats(const ws_domain *d, int32_t *last, int64_t *total, 
 /* ---- Tuning: launch shapes chosen per grid shape.
  * stencil_rows: rows each stencil workgroup streams (8, 16, 24, 32, 48 or
  * 64; taller strips repeat fewer warm-up rows, shorter ones give more
- * workgroups and a smaller last wave of workgroups).  pcr_threads: threads
+ * workgroups and a smaller last wave of workgroups) in the predictor pass,
+ * and in the corrector passes too unless corrector_rows (same choices) is
+ * set: the predictor moves twice the corrector's bytes and the corrector
+ * is bound by instruction issue, so their best heights can differ; 0 =
+ * stencil_rows for every pass.  pcr_threads: threads
  * per reduced tridiagonal system in the partitioned solve (64, 128 or 256:
  * equations held per thread versus threads per barrier).  solver: the
  * reduced systems by PCR (WS_SOLVE_PCR) or by the Thomas algorithm with one
  * lane per system (WS_SOLVE_THOMAS: linear work, no barriers, a dependent
  * chain per lane) or by factors computed once per bathymetry and boundary
  * set (WS_SOLVE_LU: the same Thomas arithmetic, two multiply-adds per unknown
- * per pass, system-interleaved storage; refactored automatically after
- * ws_set_boundary, terrain edits and ws_restore) or by such factors of a
+ * per pass, system-interleaved storage; systems of up to 512 unknowns, i.e.
+ * grids up to 4096 cells in a direction, run as one workgroup per 64
+ * systems with the systems in registers, longer ones lane per system;
+ * refactored automatically after ws_set_boundary, terrain edits and
+ * ws_restore) or by such factors of a
  * two-ended elimination (WS_SOLVE_LU2: two lanes per system meeting in the
  * middle, half the dependent chain).  Rows and threads do not change results
  * (bitwise); THOMAS and LU give the same bits; PCR and LU2 round the reduced
@@ -278,22 +285,27 @@ typedef struct {
     int32_t stencil_rows;
     int32_t pcr_threads;
     int32_t solver;
-    int32_t reserved[5];
+    int32_t corrector_rows;
+    int32_t reserved[4];
 } ws_tuning;
 ws_status ws_get_tuning(const ws_domain *d, ws_tuning *out);
 ws_status ws_set_tuning(ws_domain *d, const ws_tuning *t);
 /* Tuning of a batch (shared by its domains; default 32 rows, 128 threads). */
 ws_status ws_batch_set_tuning(ws_batch *b, const ws_tuning *t);
 /* Autotuner: times every candidate launch shape on this domain's grid
- * (corrector-pass stencil and the reduced solves, HIP events on `stream`;
- * the domain's state and history are not changed), applies the fastest and
+ * (predictor- and corrector-pass stencils and the reduced solves, HIP events
+ * on `stream`; the state, the step and the history levels the next step
+ * reads are not changed, so results are unaffected), applies the fastest and
  * returns it in *out.  With a cache file (may be NULL), a shape already
  * measured is read from it instead, and new results are appended to it as
- * lines "nx ny n_corr model stencil_rows pcr_threads".  Synchronous. */
+ * lines "nx ny n_corr model stencil_rows pcr_threads solver corrector_rows"
+ * (lines without the last field are read with corrector_rows = 0).
+ * Timing a predictor pass rewrites the history level and corrector bases
+ * the next step's predictor rewrites anyway.  Synchronous. */
 ws_status ws_tune(ws_domain *d, const char *cache_path, void *stream, ws_tuning *out);
 /* Autotuner of a batch: the same candidates timed on the batched kernels over
- * all attached domains (a corrector pass, writing only scratch), applied to
- * the batch and returned.  Synchronous. */
+ * all attached domains (predictor and corrector passes, as above), applied
+ * to the batch and returned.  Synchronous. */
 ws_status ws_batch_tune(ws_batch *b, void *stream, ws_tuning *out);
 
 /* Thread-local description of the last error. */

@@ -73,6 +73,7 @@ struct ws_domain {
     int bhealth;                   // health word as of the last batch sync
     bool vdirty;                   // pass argument tables must be rewritten
     int sy, pnt, solver;           // tuning: stencil rows per strip, PCR threads per system, reduced solver
+    int syc;                       // stencil rows per strip in corrector passes (0: sy)
     size_t fstride;                // bytes between consecutive fields
     StencilArgs *vsa;              // pass argument tables (device), batch use only
     SolveArgs *vso;
@@ -942,7 +943,8 @@ static void launch_reduced(const ws_domain *d, hipStream_t st, const SolveArgs &
 static ws_status run_pass(ws_domain *d, const StencilArgs &sa, const SolveArgs &so, hipStream_t st) {
     {
         ProfScope p(d, st, sa.kind == 2 ? WS_K_CORRECTOR : WS_K_PREDICTOR);
-        launch_stencil(d->sy, strips(d), st, sa);
+        const int rows = sa.kind == 2 && d->syc ? d->syc : d->sy;
+        launch_stencil(rows, strips_for(d, rows), st, sa);
     }
     if (!so.nlsw) {  // NLSW: identity systems, nothing to solve
         {
@@ -1069,18 +1071,19 @@ struct ws_batch {
     int max;
     BatchDesc *d_desc;
     BatchState *d_state;
-    int *d_pre[4];                       // prefix tables: stencil, tile, pcr, ghost workgroups
+    int *d_pre[5];                       // prefix tables: stencil, tile, pcr, ghost, corrector-stencil workgroups
     std::vector<ws_domain *> slots;      // attached domains by slot (nullptr = free)
     std::vector<int> order;              // slots in device table order
     std::vector<BatchState> h_state;     // host copy, device table order
     bool dirty = true;                   // tables must be rebuilt and uploaded
     bool stale = false;                  // device states ahead of the domains' host copies
-    int maxK = 0, nred = 0, total[4] = {0, 0, 0, 0};
+    int maxK = 0, nred = 0, total[5] = {0, 0, 0, 0, 0};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t gstream = nullptr;
     hipStream_t last = nullptr;
     int sy = SY, pnt = PCR_NT, solver = WS_SOLVE_PCR;  // tuning shared by all domains of the batch
+    int syc = 0;                                        // corrector-pass stencil rows (0: sy)
 };
 
 static size_t batch_layout(int max, size_t *o_state, size_t *o_pre) {
@@ -1089,7 +1092,7 @@ static size_t batch_layout(int max, size_t *o_state, size_t *o_pre) {
     size_t c = align256(sizeof(int) * (size_t)(max + 1));
     if (o_state) *o_state = a;
     if (o_pre) *o_pre = a + b;
-    return a + b + 4 * c;
+    return a + b + 5 * c;
 }
 
 static void batch_touch(ws_domain *d) {
@@ -1176,8 +1179,8 @@ static ws_status batch_upload(ws_batch *b) {
     const int n = (int)order.size();
     std::vector<BatchDesc> desc(n);
     b->h_state.assign(n, BatchState());
-    std::vector<int> pre[4];
-    for (int q = 0; q < 4; ++q) pre[q].assign(n + 1, 0);
+    std::vector<int> pre[5];
+    for (int q = 0; q < 5; ++q) pre[q].assign(n + 1, 0);
     int maxK = 0, nred = 0;
     for (int k = 0; k < n; ++k) nred = std::max(nred, nred_of(b->slots[order[k]]));
     for (int k = 0; k < n; ++k) {
@@ -1200,6 +1203,8 @@ static ws_status batch_upload(ws_batch *b) {
         const BatchDesc &D = desc[k];
         pre[0][k + 1] = pre[0][k] + D.sgx * D.sgy;
         pre[1][k + 1] = pre[1][k] + D.tgx * D.tgy;
+        const dim3 sgc = strips_for(d, b->syc ? b->syc : b->sy);
+        pre[4][k + 1] = pre[4][k] + (int)(sgc.x * sgc.y);
         pre[2][k + 1] = pre[2][k] + (b->solver == WS_SOLVE_LU2      ? solve2_waves(D.d.nx, D.d.ny)
                                      : b->solver != WS_SOLVE_PCR    ? (D.d.ny + 63) / 64 + (D.d.nx + 63) / 64
                                                                     : D.nsys);
@@ -1209,16 +1214,16 @@ static ws_status batch_upload(ws_batch *b) {
     if (n) {
         HIPCHK(hipMemcpy(b->d_desc, desc.data(), sizeof(BatchDesc) * n, hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(b->d_state, b->h_state.data(), sizeof(BatchState) * n, hipMemcpyHostToDevice));
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < 5; ++q)
             HIPCHK(hipMemcpy(b->d_pre[q], pre[q].data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice));
     }
     bool same = n == (int)b->order.size() && maxK == b->maxK && nred == b->nred;
-    for (int q = 0; q < 4; ++q) same = same && pre[q][n] == b->total[q];
+    for (int q = 0; q < 5; ++q) same = same && pre[q][n] == b->total[q];
     if (!same) batch_drop_graph(b);
     b->order = order;
     b->maxK = maxK;
     b->nred = nred;
-    for (int q = 0; q < 4; ++q) b->total[q] = pre[q][n];
+    for (int q = 0; q < 5; ++q) b->total[q] = pre[q][n];
     b->dirty = false;
     return WS_OK;
 }
@@ -1231,9 +1236,11 @@ static ws_status batch_step(ws_batch *b, hipStream_t st) {
         hipLaunchKernelGGL(kb_ghosts, dim3(b->total[3]), dim3(256), 0, st, b->d_desc, b->d_state, b->d_pre[3], n, 1);
     }
     for (int p = 0; p <= b->maxK; ++p) {
-        const dim3 sg(b->total[0]), pg(b->total[2]);
-#define L4(KERN) hipLaunchKernelGGL(KERN, sg, dim3(64 * SWG), 0, st, b->d_desc, b->d_state, b->d_pre[0], n, p)
-        SY_SWITCH(kb_stencil, b->sy, L4);
+        // predictor pass: stencil_rows; corrector passes: their own height
+        const int q = p > 0 && b->syc ? 4 : 0, rows = q ? b->syc : b->sy;
+        const dim3 sg(b->total[q]), pg(b->total[2]);
+#define L4(KERN) hipLaunchKernelGGL(KERN, sg, dim3(64 * SWG), 0, st, b->d_desc, b->d_state, b->d_pre[q], n, p)
+        SY_SWITCH(kb_stencil, rows, L4);
 #undef L4
         hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NT), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, p);
         const size_t shm = sizeof(float4) * b->nred;
@@ -1277,7 +1284,7 @@ extern "C" ws_status ws_batch_create(int32_t max_domains, void *workspace_dev, s
     b->d_desc = (BatchDesc *)base;
     b->d_state = (BatchState *)(base + o_state);
     const size_t c = align256(sizeof(int) * (size_t)(max_domains + 1));
-    for (int q = 0; q < 4; ++q) b->d_pre[q] = (int *)(base + o_pre + q * c);
+    for (int q = 0; q < 5; ++q) b->d_pre[q] = (int *)(base + o_pre + q * c);
     b->slots.assign(max_domains, nullptr);
     *out = b;
     return WS_OK;
@@ -1400,7 +1407,10 @@ static bool tuning_ok(const ws_tuning *t) {
     return t && (t->stencil_rows == 8 || t->stencil_rows == 16 || t->stencil_rows == 24 ||
                  t->stencil_rows == 32 || t->stencil_rows == 48 || t->stencil_rows == 64) &&
            (t->pcr_threads == 64 || t->pcr_threads == 128 || t->pcr_threads == 256) &&
-           (t->solver >= WS_SOLVE_PCR && t->solver <= WS_SOLVE_LU2);
+           (t->solver >= WS_SOLVE_PCR && t->solver <= WS_SOLVE_LU2) &&
+           (t->corrector_rows == 0 || t->corrector_rows == 8 || t->corrector_rows == 16 ||
+            t->corrector_rows == 24 || t->corrector_rows == 32 || t->corrector_rows == 48 ||
+            t->corrector_rows == 64);
 }
 
 extern "C" ws_status ws_get_tuning(const ws_domain *d, ws_tuning *out) {
@@ -1409,12 +1419,14 @@ extern "C" ws_status ws_get_tuning(const ws_domain *d, ws_tuning *out) {
     out->stencil_rows = d->sy;
     out->pcr_threads = d->pnt;
     out->solver = d->solver;
+    out->corrector_rows = d->syc;
     return WS_OK;
 }
 
 extern "C" ws_status ws_set_tuning(ws_domain *d, const ws_tuning *t) {
     if (!d || !tuning_ok(t)) return fail(WS_EINVAL, "ws_set_tuning: bad tuning");
     d->sy = t->stencil_rows;
+    d->syc = t->corrector_rows == t->stencil_rows ? 0 : t->corrector_rows;
     d->pnt = t->pcr_threads;
     if (d->solver != t->solver) batch_touch(d);  // argument blocks carry the solve layout
     d->solver = t->solver;
@@ -1423,8 +1435,10 @@ extern "C" ws_status ws_set_tuning(ws_domain *d, const ws_tuning *t) {
 
 extern "C" ws_status ws_batch_set_tuning(ws_batch *b, const ws_tuning *t) {
     if (!b || !tuning_ok(t)) return fail(WS_EINVAL, "ws_batch_set_tuning: bad tuning");
-    if (b->sy != t->stencil_rows || b->pnt != t->pcr_threads || b->solver != t->solver) {
+    const int syc = t->corrector_rows == t->stencil_rows ? 0 : t->corrector_rows;
+    if (b->sy != t->stencil_rows || b->syc != syc || b->pnt != t->pcr_threads || b->solver != t->solver) {
         b->sy = t->stencil_rows;
+        b->syc = syc;
         b->pnt = t->pcr_threads;
         b->solver = t->solver;
         b->dirty = true;
@@ -1437,13 +1451,17 @@ static bool cache_lookup(const char *path, const ws_grid &g, ws_tuning *t) {
     if (!path) return false;
     FILE *f = std::fopen(path, "r");
     if (!f) return false;
-    int nx, ny, k, m, sy, pn, so;
+    int nx, ny, k, m, sy, pn, so, syc;
     bool hit = false;
-    while (std::fscanf(f, "%d %d %d %d %d %d %d", &nx, &ny, &k, &m, &sy, &pn, &so) == 7) {
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+        syc = 0;
+        if (std::sscanf(line, "%d %d %d %d %d %d %d %d", &nx, &ny, &k, &m, &sy, &pn, &so, &syc) < 7) continue;
         if (nx == g.nx && ny == g.ny && k == g.n_corr && m == g.model) {
             t->stencil_rows = sy;
             t->pcr_threads = pn;
             t->solver = so;
+            t->corrector_rows = syc;
             hit = tuning_ok(t);
         }
     }
@@ -1487,22 +1505,51 @@ extern "C" ws_status ws_tune(ws_domain *d, const char *cache_path, void *stream,
     // candidates are timed round-robin over three rounds and each keeps its
     // best round, so slow drift of the clock or of other load on the device
     // does not favour whichever candidate ran first
+    // The next step's predictor pass (kind as that step takes it) rewrites
+    // only what that step's own predictor rewrites before anything reads it:
+    // the history level n, the corrector bases, the first estimate and the
+    // increments; it reads the state and the older history levels only.
+    StencilArgs sp;
+    SolveArgs sop;
+    pass_args(d, m, d->step + 1 <= 2, d->cur, (int)((d->step + 1) % 3), 0, sp, sop);
     const int rows[6] = {8, 16, 24, 32, 48, 64};
-    float t_rows[6] = {1e30f, 1e30f, 1e30f, 1e30f, 1e30f, 1e30f};
-    for (int c = 0; c < 6; ++c) launch_stencil(rows[c], strips_for(d, rows[c]), st, sa);  // warm-up
+    float t_rows[2][6];
+    for (int c = 0; c < 6; ++c) t_rows[0][c] = t_rows[1][c] = 1e30f;
+    for (int c = 0; c < 6; ++c) {  // warm-up
+        launch_stencil(rows[c], strips_for(d, rows[c]), st, sp);
+        launch_stencil(rows[c], strips_for(d, rows[c]), st, sa);
+    }
     for (int round = 0; round < 3; ++round)
-        for (int c = 0; c < 6; ++c) {
-            const dim3 grid = strips_for(d, rows[c]);
-            HIPCHK(hipEventRecord(e0, st));
-            for (int k = 0; k < reps; ++k) launch_stencil(rows[c], grid, st, sa);
-            HIPCHK(hipEventRecord(e1, st));
-            HIPCHK(hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-            t_rows[c] = ms < t_rows[c] ? ms : t_rows[c];
-        }
-    for (int c = 0; c < 6; ++c)
-        if (t_rows[c] < best_s) { best_s = t_rows[c]; best.stencil_rows = rows[c]; }
+        for (int kind = 0; kind < 2; ++kind)
+            for (int c = 0; c < 6; ++c) {
+                const dim3 grid = strips_for(d, rows[c]);
+                HIPCHK(hipEventRecord(e0, st));
+                for (int k = 0; k < reps; ++k) launch_stencil(rows[c], grid, st, kind ? sa : sp);
+                HIPCHK(hipEventRecord(e1, st));
+                HIPCHK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                t_rows[kind][c] = ms < t_rows[kind][c] ? ms : t_rows[kind][c];
+            }
+    // one height for every pass unless separate heights save at least 2 % of
+    // a step's stencil time (a single kernel instance keeps the per-kernel
+    // accounting simple; smaller differences are within the timing noise)
+    const int K = d->g.n_corr;
+    int one = 0, cp = 0, cc = 0;
+    for (int c = 1; c < 6; ++c) {
+        if (t_rows[0][c] + K * t_rows[1][c] < t_rows[0][one] + K * t_rows[1][one]) one = c;
+        if (t_rows[0][c] < t_rows[0][cp]) cp = c;
+        if (t_rows[1][c] < t_rows[1][cc]) cc = c;
+    }
+    const float t_one = t_rows[0][one] + K * t_rows[1][one], t_two = t_rows[0][cp] + K * t_rows[1][cc];
+    best_s = t_one;
+    best.stencil_rows = rows[one];
+    best.corrector_rows = 0;
+    if (K > 0 && cp != cc && t_two < 0.98f * t_one) {
+        best_s = t_two;
+        best.stencil_rows = rows[cp];
+        best.corrector_rows = rows[cc];
+    }
     // the reduced systems need valid equations: one reduction of the increments
     so.layout = 0;
     hipLaunchKernelGGL(k_reduce, tiles(d), dim3(NT), 0, st, so);
@@ -1586,8 +1633,8 @@ extern "C" ws_status ws_tune(ws_domain *d, const char *cache_path, void *stream,
     if (cache_path) {
         FILE *f = std::fopen(cache_path, "a");
         if (f) {
-            std::fprintf(f, "%d %d %d %d %d %d %d\n", d->g.nx, d->g.ny, d->g.n_corr, d->g.model, best.stencil_rows,
-                         best.pcr_threads, best.solver);
+            std::fprintf(f, "%d %d %d %d %d %d %d %d\n", d->g.nx, d->g.ny, d->g.n_corr, d->g.model, best.stencil_rows,
+                         best.pcr_threads, best.solver, best.corrector_rows);
             std::fclose(f);
         }
     }
@@ -1619,24 +1666,44 @@ extern "C" ws_status ws_batch_tune(ws_batch *b, void *stream, ws_tuning *out) {
         return ms;
     };
     const int rows[6] = {8, 16, 24, 32, 48, 64}, threads[3] = {64, 128, 256};
-    int best_sy = b->sy, best_pnt = b->pnt, best_solver = WS_SOLVE_PCR;
+    int best_sy = b->sy, best_syc = b->syc, best_pnt = b->pnt, best_solver = WS_SOLVE_PCR;
     b->solver = WS_SOLVE_PCR;  // the PCR trials use the PCR prefix table
-    float best = 1e30f;
+    float best = 1e30f, best_c = 1e30f, tp[6], tc[6];
+    for (int c = 0; c < 6; ++c) tp[c] = tc[c] = 1e30f;
+    b->syc = 0;
     for (int c = 0; c < 6; ++c) {
         b->sy = rows[c];
         b->dirty = true;
         if ((r = batch_upload(b)) != WS_OK) return r;
         const int n = (int)b->order.size();
         if (n == 0) break;
-        const float ms = time_it([&] {
-            const dim3 sg(b->total[0]);
-#define L5(KERN) hipLaunchKernelGGL(KERN, sg, dim3(64 * SWG), 0, st, b->d_desc, b->d_state, b->d_pre[0], n, 1)
-            SY_SWITCH(kb_stencil, b->sy, L5);
+        // pass 0: each domain's next predictor (it rewrites only what that
+        // step's predictor rewrites first); pass 1: a corrector (scratch only)
+        float ms[2];
+        for (int p = 0; p < 2; ++p)
+            ms[p] = time_it([&] {
+                const dim3 sg(b->total[0]);
+#define L5(KERN) hipLaunchKernelGGL(KERN, sg, dim3(64 * SWG), 0, st, b->d_desc, b->d_state, b->d_pre[0], n, p)
+                SY_SWITCH(kb_stencil, b->sy, L5);
 #undef L5
-        });
-        if (ms < best) { best = ms; best_sy = rows[c]; }
+            });
+        tp[c] = ms[0];
+        tc[c] = ms[1];
+        if (ms[0] < best) { best = ms[0]; best_sy = rows[c]; }
+        if (ms[1] < best_c) { best_c = ms[1]; best_syc = rows[c]; }
+    }
+    {
+        // as in ws_tune: separate heights only when they save 2 % of a step's
+        // stencil time (K = the batch's largest corrector count)
+        int one = 0;
+        for (int c = 1; c < 6; ++c)
+            if (tp[c] + b->maxK * tc[c] < tp[one] + b->maxK * tc[one]) one = c;
+        const bool two = b->maxK > 0 && best_sy != best_syc &&
+                         best + b->maxK * best_c < 0.98f * (tp[one] + b->maxK * tc[one]);
+        if (!two) best_sy = best_syc = rows[one];
     }
     b->sy = best_sy;
+    b->syc = best_syc == best_sy ? 0 : best_syc;
     b->dirty = true;
     if ((r = batch_upload(b)) != WS_OK) return r;
     const int n = (int)b->order.size();
@@ -1725,6 +1792,7 @@ extern "C" ws_status ws_batch_tune(ws_batch *b, void *stream, ws_tuning *out) {
     b->dirty = true;
     std::memset(out, 0, sizeof *out);
     out->stencil_rows = b->sy;
+    out->corrector_rows = b->syc;
     out->pcr_threads = b->pnt;
     out->solver = b->solver;
     return WS_OK;

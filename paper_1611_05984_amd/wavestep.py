@@ -46,7 +46,7 @@ class Boundary(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("stencil_rows", C.c_int32), ("pcr_threads", C.c_int32), ("solver", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("corrector_rows", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class WaveStepError(RuntimeError):
@@ -256,13 +256,14 @@ class Domain:
         _check(lib().ws_restore(self._h, _dptr(buf), buf.numel(), _stream(stream)), "ws_restore")
 
     def tuning(self):
-        """(stencil rows, PCR threads, reduced solver) of this domain."""
+        """(stencil rows, PCR threads, reduced solver, corrector-pass stencil
+        rows or 0 for the same as the first) of this domain."""
         t = Tuning()
         _check(lib().ws_get_tuning(self._h, C.byref(t)), "ws_get_tuning")
-        return t.stencil_rows, t.pcr_threads, t.solver
+        return t.stencil_rows, t.pcr_threads, t.solver, t.corrector_rows
 
-    def set_tuning(self, stencil_rows, pcr_threads, solver=SOLVE_PCR):
-        t = Tuning(int(stencil_rows), int(pcr_threads), int(solver))
+    def set_tuning(self, stencil_rows, pcr_threads, solver=SOLVE_PCR, corrector_rows=0):
+        t = Tuning(int(stencil_rows), int(pcr_threads), int(solver), int(corrector_rows))
         _check(lib().ws_set_tuning(self._h, C.byref(t)), "ws_set_tuning")
 
     def tune(self, cache_path=None, stream=None):
@@ -270,7 +271,7 @@ class Domain:
         t = Tuning()
         path = cache_path.encode() if cache_path else None
         _check(lib().ws_tune(self._h, path, _stream(stream), C.byref(t)), "ws_tune")
-        return t.stencil_rows, t.pcr_threads, t.solver
+        return t.stencil_rows, t.pcr_threads, t.solver, t.corrector_rows
 
     def profile(self, on=True):
         _check(lib().ws_profile_enable(self._h, 1 if on else 0), "ws_profile_enable")
@@ -318,15 +319,15 @@ class Batch:
         _check(lib().ws_batch_detach(self._h, int(slot)), "ws_batch_detach")
         return self.domains.pop(int(slot))
 
-    def set_tuning(self, stencil_rows, pcr_threads, solver=SOLVE_PCR):
-        t = Tuning(int(stencil_rows), int(pcr_threads), int(solver))
+    def set_tuning(self, stencil_rows, pcr_threads, solver=SOLVE_PCR, corrector_rows=0):
+        t = Tuning(int(stencil_rows), int(pcr_threads), int(solver), int(corrector_rows))
         _check(lib().ws_batch_set_tuning(self._h, C.byref(t)), "ws_batch_set_tuning")
 
     def tune(self):
         """Run the batch autotuner on the attached domains; returns the choice."""
         t = Tuning()
         _check(lib().ws_batch_tune(self._h, C.c_void_p(self.stream.cuda_stream), C.byref(t)), "ws_batch_tune")
-        return t.stencil_rows, t.pcr_threads, t.solver
+        return t.stencil_rows, t.pcr_threads, t.solver, t.corrector_rows
 
     def set_stop(self, slot, stop_step):
         """Do not advance the domain in `slot` past step `stop_step` (-1: no limit)."""

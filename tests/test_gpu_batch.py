@@ -228,12 +228,12 @@ def test_tunings_identical_results_and_autotuner(tmp_path):
     say("case: tunings on %s" % w.name)
     ref = make(w)
     ref.advance(30)
-    for sy, pn in [(8, 64), (16, 128), (24, 256), (48, 64), (64, 128), (32, 256)]:
+    for sy, pn, syc in [(8, 64, 0), (16, 128, 0), (24, 256, 8), (48, 64, 0), (64, 128, 16), (32, 256, 64)]:
         d = make(w)
-        d.set_tuning(sy, pn)
-        assert d.tuning() == (sy, pn, ws.SOLVE_PCR)
+        d.set_tuning(sy, pn, ws.SOLVE_PCR, syc)
+        assert d.tuning() == (sy, pn, ws.SOLVE_PCR, syc)
         d.advance(30)
-        same(ref, d, "tuning %s" % ((sy, pn),))
+        same(ref, d, "tuning %s" % ((sy, pn, syc),))
     # the lane-per-system Thomas solve of the reduced systems rounds
     # differently from PCR: equal within the parity tolerance of the solve
     th = make(w)
@@ -264,19 +264,25 @@ def test_tunings_identical_results_and_autotuner(tmp_path):
     cache = str(tmp_path / "tune.txt")
     t = d.tune(cache)
     assert t[0] in (8, 16, 24, 32, 48, 64) and t[1] in (64, 128, 256) and t[2] in (0, 1, 2, 3)
+    assert t[3] in (0, 8, 16, 24, 32, 48, 64) and t[3] != t[0]
     assert d.tuning() == t
     after = d.state_numpy()
     assert all(np.array_equal(x, y) for x, y in zip(before, after)) and d.query()[0] == 30
     line = open(cache).read().split()
-    assert [int(v) for v in line] == [w.nx, w.ny, 2, 0, t[0], t[1], t[2]]
+    assert [int(v) for v in line] == [w.nx, w.ny, 2, 0, t[0], t[1], t[2], t[3]]
     d2 = make(w)
     assert d2.tune(cache) == t                     # read from the cache
-    d.set_tuning(t[0], t[1], ws.SOLVE_PCR)        # bitwise comparable with the reference
+    old = str(tmp_path / "old.txt")                # a line without corrector rows
+    open(old, "w").write("%d %d 2 0 16 64 1\n" % (w.nx, w.ny))
+    assert make(w).tune(old) == (16, 64, ws.SOLVE_THOMAS, 0)
+    d.set_tuning(t[0], t[1], ws.SOLVE_PCR, t[3])  # bitwise comparable with the reference
     d.advance(10)
     ref.advance(10)
     same(ref, d, "after tuning")
     with pytest.raises(ws.WaveStepError):
         d.set_tuning(40, 128)
+    with pytest.raises(ws.WaveStepError):
+        d.set_tuning(8, 128, ws.SOLVE_PCR, 12)
     B = ws.Batch(4)
     b = make(w)
     B.set_tuning(24, 64)
@@ -284,7 +290,8 @@ def test_tunings_identical_results_and_autotuner(tmp_path):
     B.advance(20)
     tb = B.tune()                                  # leaves the states alone
     assert tb[0] in (8, 16, 24, 32, 48, 64) and tb[1] in (64, 128, 256) and tb[2] in (0, 1, 2, 3)
-    B.set_tuning(tb[0], tb[1], ws.SOLVE_PCR)
+    assert tb[3] in (0, 8, 16, 24, 32, 48, 64)
+    B.set_tuning(tb[0], tb[1], ws.SOLVE_PCR, tb[3])
     B.advance(20)
     B.sync()
     same(ref, b, "batch tuned 24/64, then autotuned %s" % (tb,))
