@@ -137,6 +137,18 @@ ws_status ws_domain_destroy(ws_domain *d);
 /* Boundary condition of one side (WS_WEST..WS_NORTH).  Synchronous. */
 ws_status ws_set_boundary(ws_domain *d, int32_t side, const ws_boundary *b);
 
+/* Change parameters of a running domain (the paper's interactive changes of
+ * the physical and numerical parameters, sec. 3.3): model, friction and its
+ * coefficient, B, theta, eps, g, fstar_extrap and dt take effect at the next
+ * step; nx, ny, dx, dy, n_corr and still_water must equal the current ones
+ * (WS_EINVAL).  A new dt restarts the multistep history (the next two steps
+ * are Euler steps, as after ws_set_state; the step count restarts from 0, the
+ * time goes on) and rescales partially reflective sponges; a new model or B
+ * refactors the reduced systems and is refused with WS_ENOTDD, the domain
+ * unchanged, if eq. 23 would lose diagonal dominance (that check
+ * synchronizes `stream`).  The state is kept. */
+ws_status ws_update_grid(ws_domain *d, const ws_grid *g, void *stream);
+
 /* Hot start (sec. 3.2): device arrays w (surface elevation), P, Q with row
  * pitch `pitch` elements; t is the time of this state.  Restarts the
  * multistep history (the next two steps are Euler steps). */

@@ -46,6 +46,7 @@ def lib():
         L.or_set_sponge_reflect.argtypes = [C.c_void_p, C.c_int, C.c_double]
         L.or_set_corrector_tolerance.argtypes = [C.c_void_p, C.c_double, C.c_double]
         L.or_set_n_corr.argtypes = [C.c_void_p, C.c_int]
+        L.or_update_params.argtypes = [C.c_void_p, C.POINTER(Params)]
         L.or_corrector_stats.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int64),
                                          _dp, _dp]
         L.or_set_state.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_double]
@@ -130,6 +131,20 @@ class Domain:
         <= 0: the fixed count."""
         if lib().or_set_corrector_tolerance(self._h, float(tol_w), float(tol_pq)):
             raise ValueError("oracle: bad tolerance")
+
+    def update(self, **kw):
+        """Change parameters of the running domain (fields of Params: model,
+        friction, fcoef, Bdisp, theta, eps, g, fstar_extrap, dt); a new dt
+        restarts the multistep history.  ValueError if refused."""
+        p = Params.from_buffer_copy(self.p)
+        for k, v in kw.items():
+            if not hasattr(p, k):
+                raise ValueError("unknown parameter %s" % k)
+            setattr(p, k, v)
+        rc = lib().or_update_params(self._h, C.byref(p))
+        if rc:
+            raise ValueError("oracle: parameter update refused (%d)" % rc)
+        self.p = p
 
     def set_n_corr(self, n_corr):
         """Corrector count of the following steps (the cap in tolerance mode)."""

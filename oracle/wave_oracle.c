@@ -60,6 +60,7 @@ typedef struct {
 typedef struct {
     int type, width, ncomp;
     double expo; /* sponge: exponent s of the damping factor gamma^s (1 = eq. 30) */
+    double reflect; /* sponge: target reflection coefficient it was set with (0 = eq. 30) */
     double amp[OR_MAXC], omega[OR_MAXC], k[OR_MAXC], c[OR_MAXC];
     double dirx[OR_MAXC], diry[OR_MAXC], phase[OR_MAXC];
 } or_side;
@@ -779,6 +780,7 @@ int or_set_boundary(or_domain *D, int side, int type, int width, int ncomp, cons
     s->type = type;
     s->width = width;
     s->expo = 1.0;
+    s->reflect = 0.0;
     s->ncomp = type == OR_WAVES ? ncomp : 0;
     fill_bathy_ghosts(D);
     double dref = ref_depth;
@@ -823,6 +825,38 @@ int or_set_corrector_tolerance(or_domain *D, double tol_w, double tol_pq) {
     return 0;
 }
 
+/* Change parameters of a running domain (sec. 3.3: the user may alter the
+ * physical and numerical parameters while the model runs).  nx, ny, dx, dy,
+ * n_corr and ws must stay; a new dt restarts the multistep history (the step
+ * count restarts from 0, so the next two steps are Euler steps of sec. 2.3;
+ * the time goes on) and rescales partially reflective sponges; the state is
+ * kept.  A new model or B that leaves eq. (23) without diagonal dominance is
+ * refused (-2) with the domain unchanged. */
+int or_diag_dominant(const or_domain *D);
+int or_set_sponge_reflect(or_domain *D, int side, double R);
+
+int or_update_params(or_domain *D, const or_params *p) {
+    if (!D || !p) return -1;
+    const or_params o = D->p;
+    if (p->nx != o.nx || p->ny != o.ny || p->dx != o.dx || p->dy != o.dy || p->n_corr != o.n_corr ||
+        p->ws != o.ws || !(p->dt > 0) || !(p->g > 0) || !(p->theta >= 1.0 && p->theta <= 2.0) || !(p->eps > 0) ||
+        (p->model != OR_BSNQ && p->model != OR_NLSW) || p->friction < 0 || p->friction > 2 ||
+        p->fstar_extrap < 0 || p->fstar_extrap > 2 || !(p->Bdisp >= 0) || !(p->fcoef >= 0))
+        return -1;
+    D->p = *p;
+    if (!or_diag_dominant(D)) {
+        D->p = o;
+        return -2;
+    }
+    if (p->dt != o.dt) {
+        D->step = 0;
+        for (int q = 0; q < 4; ++q)
+            if (D->side[q].type == OR_SPONGE && D->side[q].reflect > 0.0)
+                or_set_sponge_reflect(D, q, D->side[q].reflect);
+    }
+    return 0;
+}
+
 /* Corrector count of the following steps (fixed-count mode; the cap in the
  * tolerance mode). */
 int or_set_n_corr(or_domain *D, int n_corr) {
@@ -858,8 +892,10 @@ int or_corrector_stats(const or_domain *D, int *last, int64_t *total, double *dw
 int or_set_sponge_reflect(or_domain *D, int side, double R) {
     if (!D || side < 0 || side > 3 || D->side[side].type != OR_SPONGE || !(R >= 0.0 && R <= 1.0)) return -1;
     or_side *s = &D->side[side];
+    s->reflect = R;
     if (R == 0.0) {
         s->expo = 1.0;
+    s->reflect = 0.0;
         return 0;
     }
     if (R == 1.0) {
@@ -879,6 +915,7 @@ int or_set_sponge_reflect(or_domain *D, int side, double R) {
     const double L = s->width * (side == OR_WEST || side == OR_EAST ? D->p.dx : D->p.dy);
     if (!(d > 0.0)) {
         s->expo = 1.0;
+    s->reflect = 0.0;
         return 0;
     }
     const double e = -log(R) * sqrt(D->p.g * d) * D->p.dt / (4.0 * L * log(2.0));

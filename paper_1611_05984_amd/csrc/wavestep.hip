@@ -61,6 +61,7 @@ struct ws_domain {
     double *scal;                  // small device scratch (reductions)
     int side_type[4], side_width[4], side_ncomp[4];
     float side_expo[4];   // sponge damping exponent (1 = the layer of eq. 30)
+    double side_R[4], side_depth[4];  // sponge target reflection and mean side depth it was set with
     int cur;
     int64_t step;
     double t;
@@ -532,6 +533,18 @@ struct ProfScope {
     }
 };
 
+// Damping exponent of a sponge side: 1 for the layer of eq. 30, 0 for a
+// wall; for a partially reflective layer, a long wave crossing it and coming
+// back keeps the share exp(-4 s L ln 2 / (c dt)) of its amplitude.
+static float sponge_expo(const ws_domain *d, int side) {
+    const double R = d->side_R[side], dside = d->side_depth[side];
+    if (R == 1.0) return 0.f;  // no damping: a solid wall
+    if (!(R > 0.0) || !(dside > 0.0)) return 1.f;
+    const double L = d->side_width[side] * (side < 2 ? d->g.dx : d->g.dy);
+    const double e = -std::log(R) * std::sqrt(d->g.g * dside) * d->g.dt / (4.0 * L * std::log(2.0));
+    return (float)(e < 1.0 ? e : 1.0);
+}
+
 extern "C" ws_status ws_set_boundary(ws_domain *d, int32_t side, const ws_boundary *b) {
     if (!d || !b || side < 0 || side > 3) return fail(WS_EINVAL, "ws_set_boundary: bad argument");
     if (busy_check(d, "ws_set_boundary") != WS_OK) return WS_EBUSY;
@@ -555,15 +568,9 @@ extern "C" ws_status ws_set_boundary(ws_domain *d, int32_t side, const ws_bounda
         HIPCHK(hipMemcpy(&dside, d->scal, sizeof(double), hipMemcpyDeviceToHost));
         if (!(dref > 0.0)) dref = dside;
     }
-    if (R == 1.0) {
-        d->side_expo[side] = 0.f;  // no damping: a solid wall
-    } else if (R > 0.0 && dside > 0.0) {
-        // partially reflective layer: a long wave crossing it and coming back
-        // keeps the share exp(-4 s L ln 2 / (c dt)) of its amplitude
-        const double L = b->width_cells * (side < 2 ? d->g.dx : d->g.dy);
-        const double e = -std::log(R) * std::sqrt(d->g.g * dside) * d->g.dt / (4.0 * L * std::log(2.0));
-        d->side_expo[side] = (float)(e < 1.0 ? e : 1.0);
-    }
+    d->side_R[side] = R;
+    d->side_depth[side] = dside;
+    d->side_expo[side] = sponge_expo(d, side);
     if (nc > 0 && !(dref > 0.0)) return fail(WS_EINVAL, "ws_set_boundary: no positive depth along the side");
     std::vector<double> tab((size_t)MAXC * TABW, 0.0);
     const double g = d->g.g;
@@ -585,6 +592,44 @@ extern "C" ws_status ws_set_boundary(ws_domain *d, int32_t side, const ws_bounda
     HIPCHK(hipMemcpy(d->tab[side], tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
     d->side_ncomp[side] = nc;
     d->lu_valid = false;  // boundary rows of the reduced systems change
+    batch_touch(d);
+    return WS_OK;
+}
+
+extern "C" ws_status ws_update_grid(ws_domain *d, const ws_grid *g, void *stream) {
+    if (!d || !g) return fail(WS_EINVAL, "ws_update_grid: bad argument");
+    if (busy_check(d, "ws_update_grid") != WS_OK) return WS_EBUSY;
+    const ws_grid &o = d->g;
+    if (g->nx != o.nx || g->ny != o.ny || g->dx != o.dx || g->dy != o.dy || g->n_corr != o.n_corr ||
+        g->still_water != o.still_water)
+        return fail(WS_EINVAL, "ws_update_grid: nx, ny, dx, dy, n_corr and still_water are fixed at init");
+    if (!grid_ok(g) || !(g->Bcoef >= 0.0) || !(g->friction_coef >= 0.0))
+        return fail(WS_EINVAL, "ws_update_grid: parameter out of range");
+    const bool systems = g->model != o.model || g->Bcoef != o.Bcoef;  // eq. 23 coefficients change
+    if (systems) {
+        hipStream_t st = (hipStream_t)stream;
+        Dom m = make_dom(d);
+        m.model = g->model;
+        m.Bd = (float)g->Bcoef;
+        int flag = 0;
+        hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned *>(d->scal), 1);
+        hipLaunchKernelGGL(k_check_dd, cells_grid(d->g.nx, d->g.ny), dim3(256), 0, st, m, (int *)d->scal);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(&flag, d->scal, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (flag) return fail(WS_ENOTDD, "ws_update_grid: eq. 23 would lose diagonal dominance");
+    }
+    const bool restart = g->dt != o.dt;
+    d->g = *g;
+    if (restart) {
+        // the multistep history assumes one time step: restart it (the next
+        // two steps are Euler steps, as after a hot start); the partially
+        // reflective sponges scale with the time step
+        d->step = 0;
+        for (int q = 0; q < 4; ++q)
+            if (d->side_type[q] == WS_BC_SPONGE) d->side_expo[q] = sponge_expo(d, q);
+    }
+    if (systems) d->lu_valid = false;
     batch_touch(d);
     return WS_OK;
 }

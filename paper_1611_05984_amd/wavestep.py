@@ -100,6 +100,7 @@ def lib():
             "ws_batch_status": (C.c_int, [vp, i32, C.POINTER(i64), C.POINTER(f64), C.POINTER(i32)]),
             "ws_batch_sync": (C.c_int, [vp, vp]),
             "ws_set_corrector_tolerance": (C.c_int, [vp, f64, f64]),
+            "ws_update_grid": (C.c_int, [vp, C.POINTER(Grid), vp]),
             "ws_corrector_stats": (C.c_int, [vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(f64),
                                              C.POINTER(f64)]),
         }
@@ -221,6 +222,19 @@ class Domain:
         if st not in (OK, ENOTDD):
             _check(st, "ws_apply_edit")
         return st
+
+    def update(self, stream=None, **params):
+        """Change parameters of the running domain (model, friction,
+        friction_coef, Bcoef, theta, eps, g, fstar_extrap, dt); the grid
+        shape, n_corr and still_water are fixed.  A new dt restarts the
+        multistep history."""
+        g = Grid.from_buffer_copy(self.g)
+        for k, v in params.items():
+            if not hasattr(g, k):
+                raise ValueError("unknown parameter %s" % k)
+            setattr(g, k, v)
+        _check(lib().ws_update_grid(self._h, C.byref(g), _stream(stream)), "ws_update_grid")
+        self.g = g
 
     def set_corrector_tolerance(self, tol_w, tol_pq):
         """Iterate the corrector until the largest change of w is within

@@ -200,6 +200,53 @@ def test_corrector_tolerance_mode():
     B.close()
 
 
+def test_parameter_changes_while_running_parity():
+    """Runtime parameter changes on the GPU follow the oracle: quadratic
+    friction and a new theta, then a smaller time step (restarting the
+    multistep history), then the NLSW model, with the partially reflective
+    sponge rescaled to the new step.  A dispersive model the bed cannot carry
+    is refused with WS_ENOTDD and the domain runs on unchanged."""
+    ws = _ws()
+    w = _mixed_case(96, 40, seed=5)
+    gpu, ora = build_pair(w)
+    for d in (gpu, ora):
+        d.set_boundary(wl.NORTH, wl.SPONGE, 10, sponge_reflect=0.4)
+    say("case: runtime parameter changes 96x40")
+    gpu.advance(30)
+    ora.advance(30)
+    gpu.update(friction=1, friction_coef=0.01, theta=1.5)
+    ora.update(friction=1, fcoef=0.01, theta=1.5)
+    gpu.advance(30)
+    ora.advance(30)
+    check(gpu, ora, 0.03, 0.5, rel=1e-4, what="friction, theta")
+    gpu.update(dt=0.7 * w.dt)
+    ora.update(dt=0.7 * w.dt)
+    assert gpu.query()[0] == 0
+    gpu.advance(40)
+    ora.advance(40)
+    check(gpu, ora, 0.03, 0.5, rel=1e-4, what="new dt")
+    gpu.update(model=ws.NLSW)
+    ora.update(model=o.NLSW)
+    gpu.advance(30)
+    ora.advance(30)
+    check(gpu, ora, 0.03, 0.5, rel=1e-4, what="NLSW")
+    with pytest.raises(ws.WaveStepError):
+        gpu.update(nx=97)
+    nx, ny, dx = 60, 8, 0.05
+    zc = np.full(nx + 1, 0.2)
+    zc[:40], zc[40], zc[41] = -1.1, -0.1, -0.01
+    z = zc[None, :] * np.ones((ny + 1, 1))
+    d = ws.Domain(nx, ny, dx, dx, 0.002, z, model=ws.NLSW)
+    d.advance(3)
+    before = d.state_numpy()
+    with pytest.raises(ws.WaveStepError) as err:
+        d.update(model=ws.BSNQ)
+    assert err.value.status == ws.ENOTDD
+    assert all(np.array_equal(x, y) for x, y in zip(before, d.state_numpy()))
+    d.advance(3)
+    assert d.query()[0] == 6
+
+
 @pytest.mark.parametrize("params", [dict(model=1), dict(friction=1, friction_coef=0.01),
                                     dict(friction=2, friction_coef=0.02),
                                     dict(n_corr=1), dict(n_corr=3, fstar_extrap=2),

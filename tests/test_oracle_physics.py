@@ -373,6 +373,50 @@ def test_corrector_iterated_to_a_tolerance():
     assert last == 3 and dw <= tw and dpq <= tq, (last, dw, dpq, ch)
 
 
+def test_parameter_changes_while_running():
+    """Interactive parameter changes (sec. 3.3).  An update to the same values
+    changes nothing; a new time step restarts the multistep history, so it
+    equals a hot start (sec. 3.2) from the state of that moment with the new
+    time step, bit for bit; a new model that would leave eq. 23 without
+    diagonal dominance is refused and the run goes on unchanged."""
+    w = wl.config2(nx=120, ny=30, seed=4)
+    a, b = make(w), make(w)
+    a.advance(20)
+    b.advance(20)
+    b.update(theta=1.3, eps=5e-12)
+    a.advance(15)
+    b.advance(15)
+    assert all(np.array_equal(x, y) for x, y in zip(a.state(), b.state()))
+    dt2 = 0.8 * w.dt
+    b.update(dt=dt2)
+    assert b.step == 0
+    t0 = b.t
+    wst, Pst, Qst = a.state()
+    c = o.Domain(w.nx, w.ny, w.dx, w.dy, dt2, w.z)
+    for s, side in enumerate(w.sides):
+        c.set_boundary(s, side.kind, side.width, side.amp, side.period, side.theta, side.phase or None)
+    c.set_state(wst, Pst, Qst, t0)
+    b.advance(25)
+    c.advance(25)
+    assert all(np.array_equal(x, y) for x, y in zip(b.state(), c.state()))
+    assert b.step == c.step == 25 and abs(b.t - c.t) < 1e-12
+    # a cliff (cell depths 0.6 | 0.055 | dry): the depth gradient across the
+    # shallow cell is 6 where eq. 23 needs less than ~5.37 at d/dx = 1.1
+    nx, ny, dx = 60, 8, 0.05
+    zc = np.full(nx + 1, 0.2)
+    zc[:40], zc[40], zc[41] = -1.1, -0.1, -0.01
+    z = zc[None, :] * np.ones((ny + 1, 1))
+    d = o.Domain(nx, ny, dx, dx, 0.002, z, model=o.NLSW)
+    assert d.diag_dominant()
+    d.advance(3)
+    before = d.state()
+    with pytest.raises(ValueError):
+        d.update(model=o.BSNQ)
+    assert d.p.model == o.NLSW and all(np.array_equal(x, y) for x, y in zip(before, d.state()))
+    d.advance(3)
+    assert d.step == 6
+
+
 # ------------------------------------------------------------ integrator
 @pytest.mark.slow
 def test_predictor_corrector_converges_in_time():
