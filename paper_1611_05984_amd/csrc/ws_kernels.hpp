@@ -2,7 +2,8 @@
 //
 // A pass is four launches:
 //   k_stencil  column-streaming: one wave owns a strip of 64 columns (62 of
-//              them output) and walks 32 rows with a sliding register window;
+//              them output) and walks 8-64 rows (tuned) with a sliding
+//              register window;
 //              x-neighbours come from DPP lane shifts, so every face is
 //              reconstructed and fluxed once and no LDS or barrier is used.
 //              KP07 face fluxes, bottom source, dispersive and friction
@@ -16,8 +17,12 @@
 //              segment down to its first and last unknowns (partition
 //              method); writes the eliminated interior values in place and
 //              two reduced equations per segment.
-//   k_pcr      one workgroup per row and per column system: parallel cyclic
-//              reduction of the reduced tridiagonal system in LDS.
+//   reduced    the reduced tridiagonal systems, by one of four strategies:
+//              k_pcr (parallel cyclic reduction, a workgroup per system),
+//              k_thomas (a lane per system), the factored sweeps with static
+//              factors (k_luw_solve: a workgroup per 64 systems held in
+//              registers; k_lu_solve: a lane per system) and the two-ended
+//              factored sweeps (k_lu2_solve).
 //   k_expand   per tile: back substitution of every segment from its solved
 //              end values, P = P^n + dP, Q = Q^n + dQ, shoreline fix (and the
 //              sponge after the last pass).
@@ -105,9 +110,9 @@ __device__ __forceinline__ const float *ldp(const float *p, unsigned ob) {
     return reinterpret_cast<const float *>(reinterpret_cast<const char *>(p) + ob);
 }
 
-// Rows per stencil strip: a template parameter (16, 32 or 64) chosen per grid
-// shape; taller strips spend less on the 4 warm-up rows, shorter ones give
-// small grids more workgroups.
+// Rows per stencil strip: a template parameter (8, 16, 24, 32, 48 or 64)
+// chosen per grid shape; taller strips spend less on the 4 warm-up rows,
+// shorter ones give more workgroups.
 template <int SYT>
 __device__ __forceinline__ void stencil_body(const StencilArgs &A, int bx, int by) {
     const Dom &d = A.d;
@@ -356,7 +361,7 @@ constexpr int TXP = TX + 1;  // padded LDS row: segment k of row r starts at ban
 struct SolveTile {
     float rx[TY][TXP], ry[TY][TXP];   // right-hand sides / solution of the tile
     float cz[TY + 3][TX + 3];         // corner depths, corners -1 .. TX+1, -1 .. TY+1
-    float dc[TY + 2][TX + 2];         // cell still-water depth D (unclamped), cells -1..TX, -1..TY
+    float dc[TY + 2][TX + 2];         // cell still-water depth max(D, 0), cells -1..TX, -1..TY
 };
 
 // Discharge change of a wave-maker ghost over the step (first ghost layer).
@@ -401,7 +406,7 @@ __device__ __forceinline__ void stage_tile(const SolveArgs &A, SolveTile &s, int
     __syncthreads();
     for (int k = tid; k < (TX + 2) * (TY + 2); k += NT) {
         const int lx = k % (TX + 2), ly = k / (TX + 2);
-        s.dc[ly][lx] = 0.25f * ((s.cz[ly][lx] + s.cz[ly][lx + 1]) + (s.cz[ly + 1][lx] + s.cz[ly + 1][lx + 1]));
+        s.dc[ly][lx] = fmaxf(0.25f * ((s.cz[ly][lx] + s.cz[ly][lx + 1]) + (s.cz[ly + 1][lx] + s.cz[ly + 1][lx + 1])), 0.f);
     }
     __syncthreads();
 }
@@ -424,9 +429,9 @@ __device__ __forceinline__ void seg_coefs(const SolveArgs &A, const SolveTile &s
         const int i = i0 + cx, j = j0 + cy;
         float aa = 0.f, bb = 1.f, cc = 0.f;
         if (i < d.nx && j < d.ny) {
-            const float dep = fmaxf(s.dc[cy + 1][cx + 1], 0.f);
+            const float dep = s.dc[cy + 1][cx + 1];
             if (dir == 0) {
-                const float dd = (fmaxf(s.dc[cy + 1][cx + 2], 0.f) - fmaxf(s.dc[cy + 1][cx], 0.f)) * 0.5f * d.rdx;
+                const float dd = (s.dc[cy + 1][cx + 2] - s.dc[cy + 1][cx]) * 0.5f * d.rdx;
                 tri_coef(d, dep, dd, d.rdx, aa, bb, cc);
                 if (i == 0) {
                     if (is_wall(d, 0)) bb -= aa;
@@ -439,7 +444,7 @@ __device__ __forceinline__ void seg_coefs(const SolveArgs &A, const SolveTile &s
                     cc = 0.f;
                 }
             } else {
-                const float dd = (fmaxf(s.dc[cy + 2][cx + 1], 0.f) - fmaxf(s.dc[cy][cx + 1], 0.f)) * 0.5f * d.rdy;
+                const float dd = (s.dc[cy + 2][cx + 1] - s.dc[cy][cx + 1]) * 0.5f * d.rdy;
                 tri_coef(d, dep, dd, d.rdy, aa, bb, cc);
                 if (j == 0) {
                     if (is_wall(d, 2)) bb -= aa;
@@ -1115,7 +1120,9 @@ __device__ __forceinline__ void expand_body(const SolveArgs &A, SolveTile &s, in
         if (i >= d.nx || j >= d.ny) continue;
         const int o = j * d.pitch + i;
         float P = pre_p[m] + s.rx[cy][cx], Q = pre_q[m] + s.ry[cy][cx], e = pre_e[m];
-        const float Dc = s.dc[cy + 1][cx + 1];
+        // unclamped still-water depth of the cell (negative on land)
+        const float Dc = 0.25f * ((s.cz[cy + 1][cx + 1] + s.cz[cy + 1][cx + 2]) +
+                                  (s.cz[cy + 2][cx + 1] + s.cz[cy + 2][cx + 2]));
         const float h = e + Dc, h2 = h * h, h4 = h2 * h2;
         if (h4 < d.eps) {  // shoreline: discharge = h * desingularized velocity
             const float f = 1.41421356237f * h2 * frsq(h4 + d.eps);
