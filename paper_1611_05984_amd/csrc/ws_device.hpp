@@ -234,6 +234,14 @@ __device__ __forceinline__ void cu_flux(float g, float eps, float Df, const F3 &
 }
 
 // Row/column system coefficients of eq. 23 for one cell.
+__device__ __forceinline__ void tri_coef_bsnq(float Bd, float dep, float ddep, float rh, float &A, float &B,
+                                              float &C) {
+    float al = (Bd + 1.f / 3.f) * dep * dep * rh * rh;
+    float be = dep * ddep * rh * (1.f / 6.f);
+    A = be - al;
+    B = 1.f + 2.f * al;
+    C = -be - al;
+}
 __device__ __forceinline__ void tri_coef(const Dom &d, float dep, float ddep, float rh, float &A,
                                          float &B, float &C) {
     if (d.model == NLSW) {
@@ -242,11 +250,7 @@ __device__ __forceinline__ void tri_coef(const Dom &d, float dep, float ddep, fl
         C = 0.f;
         return;
     }
-    float al = (d.Bd + 1.f / 3.f) * dep * dep * rh * rh;
-    float be = dep * ddep * rh * (1.f / 6.f);
-    A = be - al;
-    B = 1.f + 2.f * al;
-    C = -be - al;
+    tri_coef_bsnq(d.Bd, dep, ddep, rh, A, B, C);
 }
 
 __device__ __forceinline__ float sponge_gamma(float dist, float Ls) {

@@ -418,11 +418,30 @@ __device__ __forceinline__ void stage_tile(const SolveArgs &A, SolveTile &s, int
 // wave maker it is the maker's known discharge, whose change over the step
 // moves to the right-hand side of the delta-form system (r, when given).
 // Padding cells are identity rows with zero right-hand side.
-template <int M>
+template <int M, bool INNER = false>
 __device__ __forceinline__ void seg_coefs(const SolveArgs &A, const SolveTile &s, int i0, int j0, int dir,
                                           int x0, int y0, float (&a)[M], float (&b)[M], float (&c)[M],
                                           float *r, int st) {
     const Dom &d = A.d;
+    // INNER: a segment clear of the domain's edges (in the dispersive model)
+    // takes a path without boundary rows, cells outside or per-cell tests;
+    // the same arithmetic as the general loop below (used where the
+    // duplicated code pays: the reduction, not the expansion)
+    const int fi = i0 + x0, fj = j0 + y0;
+    const bool inner = INNER && d.model != NLSW &&
+                       (dir == 0 ? fj < d.ny && fi >= 1 && fi + M <= d.nx - 1 : fi < d.nx && fj >= 1 && fj + M <= d.ny - 1);
+    if (inner) {
+        const float rh = dir == 0 ? d.rdx : d.rdy;
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int cx = dir == 0 ? x0 + k : x0, cy = dir == 0 ? y0 : y0 + k;
+            const float dep = s.dc[cy + 1][cx + 1];
+            const float dd = dir == 0 ? (s.dc[cy + 1][cx + 2] - s.dc[cy + 1][cx]) * 0.5f * rh
+                                      : (s.dc[cy + 2][cx + 1] - s.dc[cy][cx + 1]) * 0.5f * rh;
+            tri_coef_bsnq(d.Bd, dep, dd, rh, a[k], b[k], c[k]);
+        }
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < M; ++k) {
         const int cx = dir == 0 ? x0 + k : x0, cy = dir == 0 ? y0 : y0 + k;
@@ -535,7 +554,7 @@ __device__ __forceinline__ void reduce_body(const SolveArgs &A, SolveTile &s, in
         float a[MX], b[MX], c[MX];
         float4 first, last;
         float *r = &s.rx[row][k0];
-        seg_coefs<MX>(A, s, i0, j0, 0, k0, row, a, b, c, r, 1);
+        seg_coefs<MX, true>(A, s, i0, j0, 0, k0, row, a, b, c, r, 1);
         seg_eliminate<MX>(r, 1, a, b, c, first, last);
         const int k = 2 * (bx * (TX / MX) + seg), j = j0 + row;
         if (A.layout) {
@@ -554,7 +573,7 @@ __device__ __forceinline__ void reduce_body(const SolveArgs &A, SolveTile &s, in
         float a[TY], b[TY], c[TY];
         float4 first, last;
         float *r = &s.ry[0][col];
-        seg_coefs<TY>(A, s, i0, j0, 1, col, 0, a, b, c, r, TXP);
+        seg_coefs<TY, true>(A, s, i0, j0, 1, col, 0, a, b, c, r, TXP);
         seg_eliminate<TY>(r, TXP, a, b, c, first, last);
         const int i = i0 + col;
         if (A.layout) {
