@@ -133,6 +133,19 @@ def test_batch_edits_attach_detach_and_busy():
         for k in (0, 1, 3):
             same(alone[k], inb[k], "domain %d replay %d" % (k, step))
     same(alone[2], inb[2], "detached domain")
+    # runtime parameter changes of attached domains: friction on one, a new
+    # time step (history restart) on another; the batch follows them
+    for d in (alone[0], inb[0]):
+        d.update(friction=1, friction_coef=0.02)
+    for d in (alone[1], inb[1]):
+        d.update(dt=0.75 * cases[1][0].dt)
+    B.advance(6)
+    for k in (0, 1, 3):
+        alone[k].advance(6)
+    B.sync()
+    for k in (0, 1, 3):
+        same(alone[k], inb[k], "domain %d after parameter changes" % k)
+    assert inb[1].query()[0] == 6
     B.close()
 
 
