@@ -247,6 +247,58 @@ def test_parameter_changes_while_running_parity():
     assert d.query()[0] == 6
 
 
+def _tiny_case(nx, ny):
+    dx = 0.1
+    X = np.arange(nx + 1)[None, :] * dx
+    z = (-0.5 + 0.05 * np.sin(X)) * np.ones((ny + 1, 1))
+    sides = wl.walls()
+    sides[wl.WEST] = wl.Side(wl.WAVES, 2, [0.01], [1.0], [0.2], [0.0])
+    sides[wl.EAST] = wl.Side(wl.SPONGE, max(1, nx // 2))
+    return wl.Workload("tiny_%dx%d" % (nx, ny), nx, ny, dx, dx, wl.courant_dt(0.2, dx, 0.55), z, sides)
+
+
+@pytest.mark.parametrize("nx,ny", [(2, 2), (3, 2), (2, 7), (17, 5)])
+def test_tiny_grids(nx, ny):
+    """The smallest grids (one partial strip, one partial tile, reduced
+    systems of a few unknowns, a wave maker and a sponge wider than half the
+    domain): parity with the oracle after a water edit and 40 steps."""
+    say("case: tiny grid %dx%d" % (nx, ny))
+    w = _tiny_case(nx, ny)
+    gpu, ora = build_pair(w)
+    for d in (gpu, ora):
+        assert d.apply_edit(_ws().EDIT_WATER, 0.5 * nx * w.dx, 0.5 * ny * w.dy, 0.02, 0.1) == 0
+    gpu.advance(40)
+    ora.advance(40)
+    check(gpu, ora, 0.02, 0.5, rel=1e-4, what="tiny %dx%d" % (nx, ny))
+
+
+def test_degenerate_calls():
+    """Zero steps change nothing; an empty batch advances and syncs; a grid
+    whose reduced systems would exceed the library's limit, a bad side and a
+    bad edit kind are refused with WS_EINVAL."""
+    ws = _ws()
+    w = _tiny_case(17, 5)
+    gpu, _ = build_pair(w)
+    gpu.advance(3)
+    before = gpu.state_numpy()
+    gpu.advance(0)
+    assert gpu.query()[0] == 3 and all(np.array_equal(x, y) for x, y in zip(before, gpu.state_numpy()))
+    B = ws.Batch(2)
+    B.advance(5)
+    B.sync()
+    B.close()
+    with pytest.raises(ws.WaveStepError) as e:
+        ws.Domain(16400, 2, 0.1, 0.1, 0.01, -np.ones((3, 16401)))
+    assert e.value.status == ws.EINVAL
+    with pytest.raises(ws.WaveStepError) as e:
+        gpu.set_boundary(5, ws.SPONGE, 4)
+    assert e.value.status == ws.EINVAL
+    with pytest.raises(ws.WaveStepError) as e:
+        gpu.apply_edit(7, 0.5, 0.2, 0.01, 0.1)
+    assert e.value.status == ws.EINVAL
+    assert gpu.query()[0] == 3
+
+
 @pytest.mark.parametrize("params", [dict(model=1), dict(friction=1, friction_coef=0.01),
                                     dict(friction=2, friction_coef=0.02),
                                     dict(n_corr=1), dict(n_corr=3, fstar_extrap=2),
