@@ -942,7 +942,7 @@ static int solve2_waves(int nx, int ny) { return (2 * ny + 63) / 64 + (2 * nx + 
 // unknowns a wave), or 0 where the longest reduced system is too long for it
 // and the lane-per-system sweep runs instead.
 static int luw_waves(int nred) { return nred <= LUR * LUW_MAX ? (nred + LUR - 1) / LUR : 0; }
-static int luw_groups(int nx, int ny) { return (ny + 63) / 64 + (nx + 63) / 64; }
+static int luw_groups(int nx, int ny) { return (ny + LUS - 1) / LUS + (nx + LUS - 1) / LUS; }
 static int nred_of(const ws_domain *d) { return d->nu > d->nv ? d->nu : d->nv; }
 static bool factored(int solver) { return solver == WS_SOLVE_LU || solver == WS_SOLVE_LU2; }
 
@@ -1250,9 +1250,10 @@ static ws_status batch_upload(ws_batch *b) {
         pre[1][k + 1] = pre[1][k] + D.tgx * D.tgy;
         const dim3 sgc = strips_for(d, b->syc ? b->syc : b->sy);
         pre[4][k + 1] = pre[4][k] + (int)(sgc.x * sgc.y);
-        pre[2][k + 1] = pre[2][k] + (b->solver == WS_SOLVE_LU2      ? solve2_waves(D.d.nx, D.d.ny)
-                                     : b->solver != WS_SOLVE_PCR    ? (D.d.ny + 63) / 64 + (D.d.nx + 63) / 64
-                                                                    : D.nsys);
+        pre[2][k + 1] = pre[2][k] + (b->solver == WS_SOLVE_LU2                     ? solve2_waves(D.d.nx, D.d.ny)
+                                     : b->solver == WS_SOLVE_LU && luw_waves(nred) ? luw_groups(D.d.nx, D.d.ny)
+                                     : b->solver != WS_SOLVE_PCR                   ? (D.d.ny + 63) / 64 + (D.d.nx + 63) / 64
+                                                                                   : D.nsys);
         pre[3][k + 1] = pre[3][k] + (D.makers ? (8 * D.d.gl * GHL + 255) / 256 : 0);
         maxK = D.K > maxK ? D.K : maxK;
     }

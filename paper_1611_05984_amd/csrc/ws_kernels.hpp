@@ -847,6 +847,8 @@ __device__ __forceinline__ void lu_factor_body(const SolveArgs &A, float *lux, f
 // Unknowns of one system per wave in the workgroup form of the factored solve.
 constexpr int LUR = 32;
 constexpr int LUW_MAX = 16;  // waves per workgroup (1024 threads): systems up to LUR x LUW_MAX
+constexpr int LUS = 64;      // systems per workgroup, one a lane (32, with lanes l and l + 32
+                             // on the same system, doubles the workgroups and gains nothing)
 
 // The workgroup form of the one-ended sweeps, for systems of at most
 // LUR x (waves in the workgroup) unknowns: a workgroup takes 64 systems, lane
@@ -886,8 +888,8 @@ __device__ __forceinline__ void luw_solve(int N, int nsys, int s0, const float *
     const int lane = threadIdx.x & 63;
     const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int G = blockDim.x >> 6;
-    const int s = min(s0 + lane, nsys - 1);
-    const bool live = s0 + lane < nsys;
+    const int s = min(s0 + lane % LUS, nsys - 1);
+    const bool live = lane < LUS && s0 + lane < nsys;
     const int k0 = q * LUR;
     const size_t n = (size_t)N * nsys;
     const auto br = bres(r, 4 * n), bf = bres(fai, 8 * n), bc = bres(fcp, 4 * n), bx = bres(x, 4 * n);
@@ -954,15 +956,15 @@ __device__ __forceinline__ void luw_solve(int N, int nsys, int s0, const float *
     for (int t = q - 1; t >= 0; --t) lds_barrier();
 }
 
-// Workgroups 0 .. ceil(ny/64)-1 take the row systems, the rest the columns.
+// Workgroups 0 .. ceil(ny/LUS)-1 take the row systems, the rest the columns.
 __device__ __forceinline__ void luw_solve_body(const SolveArgs &A, int wg, float *slot) {
     const Dom &d = A.d;
-    const int xw = (d.ny + 63) / 64;
+    const int xw = (d.ny + LUS - 1) / LUS;
     if (wg < xw)
-        luw_solve(d.nu, d.ny, wg * 64, reinterpret_cast<const float *>(A.redx),
+        luw_solve(d.nu, d.ny, wg * LUS, reinterpret_cast<const float *>(A.redx),
                   reinterpret_cast<const float2 *>(A.lux), A.lux + 2 * (size_t)d.nu * d.ny, A.solx, slot);
     else
-        luw_solve(d.nv, d.nx, (wg - xw) * 64, reinterpret_cast<const float *>(A.redy),
+        luw_solve(d.nv, d.nx, (wg - xw) * LUS, reinterpret_cast<const float *>(A.redy),
                   reinterpret_cast<const float2 *>(A.luy), A.luy + 2 * (size_t)d.nv * d.nx, A.soly, slot);
 }
 
