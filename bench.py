@@ -70,6 +70,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="wall seconds of the session-serving run (0: skip)")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-no-recover", action="store_true",
+                    help="retire failed sessions instead of rolling them back into NLSW")
     ap.add_argument("--no-k-variants", action="store_true",
                     help="skip the K = 0 and K = 1 corrector-count rates")
     return ap.parse_args()
@@ -164,10 +166,12 @@ def batched_vs_plain(args, torch, ws, wl):
 def serving(args):
     """Session serving: the Poisson trace (4 sessions/s, grids 512^2..2048^2,
     an edit every 50 steps) served with continuous batching for a bounded
-    wall-time window."""
+    wall-time window; failed sessions are rolled back to their last edit
+    pause and continued in NLSW unless --serve-no-recover."""
     from paper_1611_05984_amd import serving as sv
     from paper_1611_05984_amd import workloads as wl
-    srv = sv.Server(budget_bytes=int(args.serve_budget_gb * 2**30), max_sessions=256, tick_steps=10)
+    srv = sv.Server(budget_bytes=int(args.serve_budget_gb * 2**30), max_sessions=256, tick_steps=10,
+                    recover=not args.serve_no_recover)
     rep = srv.run(wl.config5_trace(), wall_limit=args.serve_seconds,
                   log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
     rep["workload"] = "sessions_poisson4ps_512-2048_edits50"

@@ -194,6 +194,9 @@ ws_status ws_apply_edit(ws_domain *d, int32_t kind, double x0, double y0, double
  * asynchronously.  Stepping on after a restore continues the run exactly as
  * it would have continued from the snapshot. */
 size_t ws_snapshot_bytes(const ws_domain *d);
+/* The same for a grid not yet created (0 if the grid is invalid): what a
+ * caller budgeting device memory for a domain and its checkpoint needs. */
+size_t ws_snapshot_bytes_grid(const ws_grid *g);
 ws_status ws_snapshot(ws_domain *d, void *dst_dev, size_t bytes, void *stream);
 ws_status ws_restore(ws_domain *d, const void *src_dev, size_t bytes, void *stream);
 

@@ -648,6 +648,12 @@ struct SnapHeader {
 };
 static const unsigned long long SNAP_MAGIC = 0x3130504e53535757ull;  // "WWSSNP01"
 
+extern "C" size_t ws_snapshot_bytes_grid(const ws_grid *g) {
+    if (!grid_ok(g)) return 0;
+    const Layout L = layout(g);
+    return 256 + 18 * sizeof(float) * (size_t)L.nyp * L.pitch + sizeof(float) * (size_t)(g->ny + 1) * L.zpitch;
+}
+
 static size_t snap_field_bytes(const ws_domain *d) { return sizeof(float) * (size_t)d->nyp * d->pitch; }
 static size_t snap_corner_bytes(const ws_domain *d) { return sizeof(float) * (size_t)(d->g.ny + 1) * d->zpitch; }
 

@@ -83,6 +83,7 @@ def lib():
             "ws_profile_enable": (C.c_int, [vp, i32]),
             "ws_profile_collect": (C.c_int, [vp, vp, C.POINTER(f64), C.POINTER(i64), i32]),
             "ws_snapshot_bytes": (sz, [vp]),
+            "ws_snapshot_bytes_grid": (sz, [C.POINTER(Grid)]),
             "ws_snapshot": (C.c_int, [vp, vp, sz, vp]),
             "ws_restore": (C.c_int, [vp, vp, sz, vp]),
             "ws_get_tuning": (C.c_int, [vp, C.POINTER(Tuning)]),
@@ -140,6 +141,10 @@ def grid(nx, ny, dx, dy, dt, **kw) -> Grid:
 
 def workspace_bytes(g: Grid) -> int:
     return int(lib().ws_workspace_bytes(C.byref(g)))
+
+
+def snapshot_bytes(g: Grid) -> int:
+    return int(lib().ws_snapshot_bytes_grid(C.byref(g)))
 
 
 class Domain:
@@ -258,11 +263,13 @@ class Domain:
             _check(st, "ws_query")
         return step.value, t.value, health.value
 
-    def snapshot(self, stream=None):
-        """Device snapshot (uint8 tensor) of state, history, bathymetry, step and time."""
+    def snapshot(self, stream=None, out=None):
+        """Device snapshot (uint8 tensor) of state, history, bathymetry, step
+        and time; into `out` when it is given and large enough."""
         import torch
         n = int(lib().ws_snapshot_bytes(self._h))
-        buf = torch.empty(n, dtype=torch.uint8, device=self.device)
+        buf = out if out is not None and out.numel() >= n else torch.empty(n, dtype=torch.uint8,
+                                                                            device=self.device)
         _check(lib().ws_snapshot(self._h, _dptr(buf), n, _stream(stream)), "ws_snapshot")
         return buf
 

@@ -70,3 +70,44 @@ def test_failed_session_is_retired_and_isolated():
         mw, mP, mQ, mlog = srv.results[rid]
         assert ahealth == 0 and mlog == alog
         assert np.array_equal(mw, aw) and np.array_equal(mP, aP) and np.array_equal(mQ, aQ), rid
+
+
+def test_failed_session_recovers_in_nlsw():
+    """Recovery on: session 16 of the seed-5 serving trace (512 x 512 cells,
+    depth 0.57 m, an edit every 50 steps) goes non-finite in the dispersive
+    model (step 760) once its edits have built steep terrain with thin, fast
+    flow.  The server rolls it back to its checkpoint of the last edit pause,
+    continues it in NLSW with half the time step and runs it to its end.  A
+    session at Courant 20 fails again after every rollback and is retired
+    after the third.  Every finished session equals its run alone under the
+    same policy, bit for bit, edit statuses included."""
+    import dataclasses
+    from paper_1611_05984_amd import serving as sv
+    s16 = wl.config5_trace(seed=5, duration=20.0)[16]
+    s16 = dataclasses.replace(s16, arrival=0.0, steps=1000, edits=[e for e in s16.edits if e[0] <= 1000])
+    small = wl.config5_trace(rate=40.0, duration=0.2, seed=53, sizes=(48, 64), edit_every=20, steps=(40, 120),
+                             sigma_cells=(3, 8), water_amp=(0.02, 0.1), terrain_amp=(0.05, 0.2))[:3]
+    c20 = dataclasses.replace(small[0], courant=20.0)
+    trace = [s16, c20] + small[1:]
+    say("case: session 16 of seed 5 (512^2, 1000 steps), one Courant-20 session, %d small" % (len(trace) - 2))
+    base = sv.replay_alone(s16)
+    say("  alone without recovery: health %d" % base[4])
+    assert base[4] != 0                        # the dispersive run does fail
+    srv = sv.Server(budget_bytes=1 << 34, max_sessions=4, tick_steps=10, keep_results=True, recover=True,
+                    max_recoveries=3)
+    rep = srv.run(trace)
+    say("  report: %s" % rep)
+    say("  rollbacks: %s" % srv.recovered)
+    assert set(srv.recovered) == {0, 1} and srv.recovered[1] == 3 and set(srv.failures) == {1}
+    assert rep["sessions_done"] == len(trace) - 1
+    for rid, spec in enumerate(trace):
+        aw, aP, aQ, alog, ahealth = sv.replay_alone(spec, max_recoveries=3)
+        if rid == 1:
+            assert ahealth != 0
+            continue
+        mw, mP, mQ, mlog = srv.results[rid]
+        assert ahealth == 0 and mlog == alog and len(mlog) == len(spec.edits) - (spec.edits[-1][0] == spec.steps)
+        for m, a, f in ((mw, aw, "w"), (mP, aP, "P"), (mQ, aQ, "Q")):
+            assert np.isfinite(m).all()
+            assert np.array_equal(m, a), (rid, f, float(np.abs(m - a).max()))
+    say("  recovered session finished in NLSW; all finished sessions equal alone")
