@@ -261,7 +261,7 @@ def main():
                 sum(ALG_WORDS[c] * prof[c][1] for c in cs)) for f, cs in FUNCS.items()}
     dom_func = max(fsum, key=lambda f: fsum[f][0])
     # kernel symbol as the profiler names it (template instance of the tuned shape)
-    dom_name = {"k_stencil": "k_stencil<%d>" % tuning[0],
+    dom_name = {"k_stencil": "k_stencil_p<%d>,k_stencil_c<%d>" % (tuning[0], tuning[3] or tuning[0]),
                 "reduced_solve": ("k_pcr", "k_thomas", "k_luw_solve", "k_lu2_solve")[tuning[2]]}.get(dom_func, dom_func)
     dom_ms, dom_n, dom_words = fsum[dom_func]
     avg_s = dom_ms / dom_n / 1e3

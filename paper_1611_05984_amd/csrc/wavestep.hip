@@ -825,7 +825,9 @@ static void launch_stencil(int sy, dim3 grid, hipStream_t st, const StencilArgs 
     const dim3 g1(grid.x * grid.y);  // 1-D grid in XCD-aware tile order
     const int gx = (int)grid.x;
 #define L3(KERN) hipLaunchKernelGGL(KERN, g1, dim3(64 * SWG), 0, st, sa, gx)
-    SY_SWITCH(k_stencil, sy, L3);
+    if (sa.kind == 2) SY_SWITCH(k_stencil_c, sy, L3);
+    else if (sa.kind == 1) SY_SWITCH(k_stencil_p, sy, L3);
+    else SY_SWITCH(k_stencil_e, sy, L3);
 #undef L3
 }
 // Equations per thread for systems of up to nred unknowns: a power of two.
@@ -1292,7 +1294,8 @@ static ws_status batch_step(ws_batch *b, hipStream_t st) {
         const int q = p > 0 && b->syc ? 4 : 0, rows = q ? b->syc : b->sy;
         const dim3 sg(b->total[q]), pg(b->total[2]);
 #define L4(KERN) hipLaunchKernelGGL(KERN, sg, dim3(64 * SWG), 0, st, b->d_desc, b->d_state, b->d_pre[q], n, p)
-        SY_SWITCH(kb_stencil, rows, L4);
+        if (p > 0) SY_SWITCH(kb_stencil_c, rows, L4);
+        else SY_SWITCH(kb_stencil, rows, L4);
 #undef L4
         hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NT), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, p);
         const size_t shm = sizeof(float4) * b->nred;
@@ -1736,7 +1739,8 @@ extern "C" ws_status ws_batch_tune(ws_batch *b, void *stream, ws_tuning *out) {
             ms[p] = time_it([&] {
                 const dim3 sg(b->total[0]);
 #define L5(KERN) hipLaunchKernelGGL(KERN, sg, dim3(64 * SWG), 0, st, b->d_desc, b->d_state, b->d_pre[0], n, p)
-                SY_SWITCH(kb_stencil, b->sy, L5);
+                if (p > 0) SY_SWITCH(kb_stencil_c, b->sy, L5);
+                else SY_SWITCH(kb_stencil, b->sy, L5);
 #undef L5
             });
         tp[c] = ms[0];

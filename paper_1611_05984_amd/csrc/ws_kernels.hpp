@@ -1,7 +1,8 @@
 // ws_kernels.hpp -- the gfx950 kernels of one predictor/corrector pass.
 //
 // A pass is four launches:
-//   k_stencil  column-streaming: one wave owns a strip of 64 columns (62 of
+//   k_stencil_{e,p,c}  (Euler predictor, AB3 predictor, AM4 corrector)
+//              column-streaming: one wave owns a strip of 64 columns (62 of
 //              them output) and walks 8-64 rows (tuned) with a sliding
 //              register window;
 //              x-neighbours come from DPP lane shifts, so every face is
@@ -113,9 +114,12 @@ __device__ __forceinline__ const float *ldp(const float *p, unsigned ob) {
 // Rows per stencil strip: a template parameter (8, 16, 24, 32, 48 or 64)
 // chosen per grid shape; taller strips spend less on the 4 warm-up rows,
 // shorter ones give more workgroups.
-template <int SYT>
+// The pass kind (A.kind) is a compile-time parameter: each kernel carries
+// no code, registers or branches for the other kinds.
+template <int SYT, int KIND>
 __device__ __forceinline__ void stencil_body(const StencilArgs &A, int bx, int by) {
     const Dom &d = A.d;
+    constexpr int kind = KIND;
     const int lane = threadIdx.x & 63;
     const int strip = bx * SWG + (threadIdx.x >> 6);
     const int c0 = strip * SO - 1;  // column of lane 0; lanes 1..62 are output columns
@@ -204,12 +208,12 @@ __device__ __forceinline__ void stencil_body(const StencilArgs &A, int bx, int b
             float E1v = 0.f, F1v = 0.f, G1v = 0.f, Fs1v = 0.f, Gs1v = 0.f, E2v = 0.f, F2v = 0.f, G2v = 0.f;
             float Fs2v = 0.f, Gs2v = 0.f, Sev = 0.f, SUv = 0.f, SVv = 0.f;
             if (out) {
-                if (A.kind == 1) {
+                if (kind == 1) {
                     E1v = ldo(A.h1, o); F1v = ldo(A.h1, o + F1); G1v = ldo(A.h1, o + F2);
                     Fs1v = ldo(A.h1, o + F3b); Gs1v = ldo(A.h1, o + F4);
                     E2v = ldo(A.h2, o); F2v = ldo(A.h2, o + F1); G2v = ldo(A.h2, o + F2);
                     if (A.x2 != 0.f) { Fs2v = ldo(A.h2, o + F3b); Gs2v = ldo(A.h2, o + F4); }
-                } else if (A.kind == 2) {
+                } else if (kind == 2) {
                     Sev = ldo(A.S, o); SUv = ldo(A.S, o + F1); SVv = ldo(A.S, o + F2);
                 }
             }
@@ -272,11 +276,11 @@ __device__ __forceinline__ void stencil_body(const StencilArgs &A, int bx, int b
             if (out) {
                 const float dt = A.dt;
                 float en, U, V;  // new surface, increments of U*, V* over the step
-                if (A.kind == 0) {
+                if (kind == 0) {
                     en = e2 + dt * E;
                     U = dt * F;
                     V = dt * G;
-                } else if (A.kind == 1) {
+                } else if (kind == 1) {
                     const float c12 = dt * (1.f / 12.f), c24 = dt * (1.f / 24.f);
                     if (A.write_S) {
                         sto(A.S, o, e2 + c24 * (19.f * E - 5.f * E1v + E2v));
@@ -292,7 +296,7 @@ __device__ __forceinline__ void stencil_body(const StencilArgs &A, int bx, int b
                     U = SUv + c9 * F + Fs;
                     V = SVv + c9 * G + Gs;
                 }
-                if (A.kind != 2) {
+                if (kind != 2) {
                     sto(A.h0, o, E);
                     sto(A.h0, o + F1, F);
                     sto(A.h0, o + F2, G);
@@ -328,11 +332,25 @@ __device__ __forceinline__ void xcd_tile(int b, int G, int gx, int &bx, int &by)
     bx = t - by * gx;
 }
 
-template <int SYT>
-__global__ __launch_bounds__(64 * SWG) __attribute__((amdgpu_waves_per_eu(4))) void k_stencil(StencilArgs A, int gx) {
+// One kernel per pass kind: Euler start-up predictor, AB3 predictor, AM4
+// corrector.
+template <int SYT, int KIND>
+__device__ __forceinline__ void stencil_kernel_body(const StencilArgs &A, int gx) {
     int bx, by;
     xcd_tile(blockIdx.x, gridDim.x, gx, bx, by);
-    stencil_body<SYT>(A, bx, by);
+    stencil_body<SYT, KIND>(A, bx, by);
+}
+template <int SYT>
+__global__ __launch_bounds__(64 * SWG) __attribute__((amdgpu_waves_per_eu(4))) void k_stencil_e(StencilArgs A, int gx) {
+    stencil_kernel_body<SYT, 0>(A, gx);
+}
+template <int SYT>
+__global__ __launch_bounds__(64 * SWG) __attribute__((amdgpu_waves_per_eu(4))) void k_stencil_p(StencilArgs A, int gx) {
+    stencil_kernel_body<SYT, 1>(A, gx);
+}
+template <int SYT>
+__global__ __launch_bounds__(64 * SWG) __attribute__((amdgpu_waves_per_eu(4))) void k_stencil_c(StencilArgs A, int gx) {
+    stencil_kernel_body<SYT, 2>(A, gx);
 }
 
 // ------------------------------------------------------------- solver parts

@@ -100,8 +100,9 @@ def main():
     ap.add_argument("--out")
     ap.add_argument("--traffic-json")
     ap.add_argument("--command", default="")
-    ap.add_argument("--kernel", default="k_stencil<16>",
-                    help="kernel (as the trace names it, without namespace) whose traffic goes to --traffic-json")
+    ap.add_argument("--kernel", default="k_stencil_p<8>,k_stencil_c<8>",
+                    help="kernel, or comma-separated kernels taken as one group (as the trace names "
+                         "them, without namespace), whose traffic goes to --traffic-json")
     ap.add_argument("--sq", help="database of a rocprofv3 --pmc SQ_INSTS_VALU ... run (VALU table)")
     ap.add_argument("--skip", type=int, default=2,
                     help="leading dispatches per kernel left out of the averages (Euler start-up)")
@@ -140,12 +141,16 @@ def main():
     print(text)
     if a.out:
         open(a.out, "w").write(text + "\n")
-    if a.traffic_json and a.kernel in traffic:
+    names = a.kernel.split(",")
+    if a.traffic_json and all(n in traffic for n in names):
+        # one kernel, or a group (the predictor and corrector stencils): the
+        # average over all dispatches of the group
         root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-        t = traffic[a.kernel]
-        json.dump({"kernel": a.kernel, "bytes_per_launch": t["read"] + t["write"],
-                   "read": t["read"], "write": t["write"], "dispatches": t["dispatches"],
-                   "source_hash": source_hash(root), "command": a.command},
+        n = sum(traffic[k]["dispatches"] for k in names)
+        rd = sum(traffic[k]["read"] * traffic[k]["dispatches"] for k in names) / n
+        wr = sum(traffic[k]["write"] * traffic[k]["dispatches"] for k in names) / n
+        json.dump({"kernel": a.kernel, "bytes_per_launch": rd + wr, "read": rd, "write": wr,
+                   "dispatches": n, "source_hash": source_hash(root), "command": a.command},
                   open(a.traffic_json, "w"), indent=1)
 
 
