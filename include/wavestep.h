@@ -74,7 +74,9 @@ enum { WS_READ_W = 0, WS_READ_H = 1 };                           /* first field 
  * The first two steps after ws_domain_init / ws_set_state are first-order
  * Euler steps without correctors (sec. 2.3). */
 typedef struct {
-    int32_t nx, ny;          /* cells, >= 2 each                                  */
+    int32_t nx, ny;          /* cells, >= 2 each; five padded fields (nx rounded  */
+                             /* up to 64, ny to 16, 4 B a cell) must stay under   */
+                             /* 4 GiB: about 2.1e8 cells (e.g. 14592 x 14592)     */
     int32_t n_corr;          /* corrector passes per step [2]                     */
     int32_t model;           /* WS_BSNQ or WS_NLSW [WS_BSNQ]                      */
     int32_t friction;        /* WS_FRIC_* [WS_FRIC_NONE]                          */

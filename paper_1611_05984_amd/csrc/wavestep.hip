@@ -100,8 +100,17 @@ struct Layout {
     int nvar;
 };
 
+// The stencil addresses the fields of a group (up to five, one field stride
+// apart) by 32-bit byte offsets from the group's base: five padded fields
+// must span less than 4 GiB (about 2.1e8 cells, e.g. 14592 x 14592).
+static bool offsets_fit(const ws_grid *g) {
+    if (g->nx > (1 << 20) || g->ny > (1 << 20)) return false;
+    const size_t field = align256(sizeof(float) * (size_t)roundup(g->ny, TY) * (size_t)roundup(g->nx, TX));
+    return 5 * field <= 0xFFFFFFFFull;
+}
+
 static bool grid_ok(const ws_grid *g) {
-    return g && g->nx >= 2 && g->ny >= 2 && g->dx > 0 && g->dy > 0 && g->dt > 0 && g->g > 0 &&
+    return g && g->nx >= 2 && g->ny >= 2 && offsets_fit(g) && g->dx > 0 && g->dy > 0 && g->dt > 0 && g->g > 0 &&
            g->n_corr >= 0 && g->n_corr <= 64 && (g->model == WS_BSNQ || g->model == WS_NLSW) &&
            g->friction >= 0 && g->friction <= 2 && g->fstar_extrap >= 0 && g->fstar_extrap <= 2 &&
            g->theta >= 1.0 && g->theta <= 2.0 && g->eps > 0;
