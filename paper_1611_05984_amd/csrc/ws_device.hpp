@@ -145,9 +145,12 @@ __device__ inline void load_cell(const Dom &d, const float *__restrict__ E,
 }
 
 // ---------------------------------------------------------------- KP07 parts
+// minmod of three: the smallest if all are positive, the largest if all are
+// negative, else 0 -- the median of (min, max, 0) (v_med3: three
+// instructions with v_min3 and v_max3).
 __device__ __forceinline__ float minmod3(float a, float b, float c) {
     const float mn = fminf(a, fminf(b, c)), mx = fmaxf(a, fmaxf(b, c));
-    return mn > 0.f ? mn : (mx < 0.f ? mx : 0.f);
+    return __builtin_amdgcn_fmed3f(mn, mx, 0.f);
 }
 
 // Hardware reciprocal, reciprocal square root and square root (1 ulp); their

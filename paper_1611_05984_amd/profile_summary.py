@@ -76,9 +76,11 @@ def sq_table(sq_db, trace_db, cells):
     for name, counter, v in _q(sq_db, "select kernel_name, counter_name, value from counters_collection"):
         per[short(name)][counter].append(float(v))
     avg_us = {short(n): a for n, _, _, a, _ in trace_table(trace_db)}
-    lines = ["VALU issue peak (non-packed FP32): 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = %.1fe12 "
-             "lane-instructions/s" % (VALU_PEAK / 1e12),
-             "%-20s %13s %15s %11s %10s" % ("kernel", "VALU/disp", "lane-instr/cell", "avg_us", "VALU util")]
+    lines = ["VALU rate against one wave64 instruction per 4 cycles per SIMD: 256 CU x 4 SIMD x 16 lanes "
+             "x 2.4 GHz = %.1fe12 lane-instructions/s" % (VALU_PEAK / 1e12),
+             "(a rate above 100% means gfx950 issues some VALU instructions faster than that model, so "
+             "it is a reference, not a ceiling)",
+             "%-20s %13s %15s %11s %10s" % ("kernel", "VALU/disp", "lane-instr/cell", "avg_us", "VALU rate")]
     for k in sorted(per):
         if k not in avg_us or "SQ_INSTS_VALU" not in per[k]:
             continue
