@@ -1304,7 +1304,10 @@ static ws_status batch_step(ws_batch *b, hipStream_t st) {
         const dim3 sg(b->total[q]), pg(b->total[2]);
 #define L4(KERN) hipLaunchKernelGGL(KERN, sg, dim3(64 * SWG), 0, st, b->d_desc, b->d_state, b->d_pre[q], n, p)
         if (p > 0) SY_SWITCH(kb_stencil_c, rows, L4);
-        else SY_SWITCH(kb_stencil, rows, L4);
+        else {
+            SY_SWITCH(kb_stencil_e, rows, L4);
+            SY_SWITCH(kb_stencil_p, rows, L4);
+        }
 #undef L4
         hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NT), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, p);
         const size_t shm = sizeof(float4) * b->nred;
@@ -1749,7 +1752,7 @@ extern "C" ws_status ws_batch_tune(ws_batch *b, void *stream, ws_tuning *out) {
                 const dim3 sg(b->total[0]);
 #define L5(KERN) hipLaunchKernelGGL(KERN, sg, dim3(64 * SWG), 0, st, b->d_desc, b->d_state, b->d_pre[0], n, p)
                 if (p > 0) SY_SWITCH(kb_stencil_c, b->sy, L5);
-                else SY_SWITCH(kb_stencil, b->sy, L5);
+                else SY_SWITCH(kb_stencil_p, b->sy, L5);
 #undef L5
             });
         tp[c] = ms[0];

@@ -81,28 +81,35 @@ __device__ __forceinline__ int find_dom(const int *prefix, int ndom, int b) {
     return lo;
 }
 
-// KIND: 2 for the corrector passes; -1 for the predictor pass, Euler or AB3
-// by each domain's step (one uniform branch into the same bodies as the
-// single-domain kernels, so both give the same bits).
+// KIND: 0 for the predictor pass of domains in their Euler start-up, 1 for
+// that of domains taking full steps (each domain's predictor runs in exactly
+// one of the two launches), 2 for the corrector passes.  The bodies are the
+// single-domain kernels' own, so both give the same bits.
 template <int SYT, int KIND>
 __device__ __forceinline__ void kb_stencil_body(const BatchDesc *__restrict__ descs, const BatchState *__restrict__ states,
                                                 const int *__restrict__ prefix, int ndom, int p) {
     // XCD-aware order over all strips of all domains (as in k_stencil_*)
     const int b = xcd_order(blockIdx.x, gridDim.x), dm = find_dom(prefix, ndom, b);
     const BatchDesc &D = descs[dm];
-    const int v = variant(D, states[dm], p);
+    const BatchState &S = states[dm];
+    if (KIND < 2 && (S.step + 1 <= 2) != (KIND == 0)) return;  // the other predictor launch's domain
+    const int v = variant(D, S, p);
     if (v < 0) return;
     const int local = b - prefix[dm];
     const StencilArgs A = load_params(D.sa + v);
-    if constexpr (KIND == 2) stencil_body<SYT, 2>(A, local % D.sgx, local / D.sgx);
-    else if (A.kind == 1) stencil_body<SYT, 1>(A, local % D.sgx, local / D.sgx);
-    else stencil_body<SYT, 0>(A, local % D.sgx, local / D.sgx);
+    stencil_body<SYT, KIND>(A, local % D.sgx, local / D.sgx);
 }
 template <int SYT>
-__global__ __launch_bounds__(64 * SWG) __attribute__((amdgpu_waves_per_eu(4))) void kb_stencil(const BatchDesc *__restrict__ descs,
-                                                       const BatchState *__restrict__ states,
-                                                       const int *__restrict__ prefix, int ndom, int p) {
-    kb_stencil_body<SYT, -1>(descs, states, prefix, ndom, p);
+__global__ __launch_bounds__(64 * SWG) __attribute__((amdgpu_waves_per_eu(4))) void kb_stencil_e(const BatchDesc *__restrict__ descs,
+                                                         const BatchState *__restrict__ states,
+                                                         const int *__restrict__ prefix, int ndom, int p) {
+    kb_stencil_body<SYT, 0>(descs, states, prefix, ndom, p);
+}
+template <int SYT>
+__global__ __launch_bounds__(64 * SWG) __attribute__((amdgpu_waves_per_eu(4))) void kb_stencil_p(const BatchDesc *__restrict__ descs,
+                                                         const BatchState *__restrict__ states,
+                                                         const int *__restrict__ prefix, int ndom, int p) {
+    kb_stencil_body<SYT, 1>(descs, states, prefix, ndom, p);
 }
 template <int SYT>
 __global__ __launch_bounds__(64 * SWG) __attribute__((amdgpu_waves_per_eu(4))) void kb_stencil_c(const BatchDesc *__restrict__ descs,
