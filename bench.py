@@ -29,19 +29,19 @@ TUNING_CACHE = os.path.join(ROOT, "paper_1611_05984_amd", "tuning_cache.txt")
 #              history n-2 (E, F, G); writes history n (5), corrector bases (3),
 #              eta, dU*, dV*                                 -> 12 + 11 = 23
 #   corrector: reads eta, P, Q, depth, bases (3); writes eta, dU*, dV* -> 7 + 3 = 10
-#   reduce:    reads dU*, dV*, depth; writes the eliminated values and, per
-#              16-cell row segment and 16-cell column segment, two reduced
-#              equations (4 words each; PCR and lane Thomas) or two right-hand
-#              sides (factored solve)                       -> 3 + 2 + 1 or 0.25
+#   reduce:    reads dU*, dV*, depth; writes, per 16-cell row segment and
+#              16-cell column segment, two reduced equations (4 words each;
+#              PCR and lane Thomas) or two right-hand sides (factored solve)
+#                                                           -> 3 + 1 or 0.25
 #   reduced solve: PCR reads the equations, writes the solutions: 1 + 0.25;
 #              lane Thomas also writes and rereads its sweep values: 1 + 0.5 +
 #              0.5 + 0.25; the factored solves (one- or two-ended) read the
 #              right-hand sides and three factors, write the solutions:
 #              0.25 + 0.75 + 0.25
-#   expand:    reads eliminated values (2), P^n, Q^n, eta, depth, end values;
+#   expand:    reads dU*, dV* (2), P^n, Q^n, eta, depth, end values;
 #              writes P, Q                                  -> 6.25 + 2
 def alg_words(solver):
-    reduce_w = 5.25 if solver in (2, 3) else 6.0
+    reduce_w = 3.25 if solver in (2, 3) else 4.0
     solve_w = {0: 1.25, 1: 2.25, 2: 1.25, 3: 1.25}[solver]
     return {"k_stencil[predictor]": 23.0, "k_stencil[corrector]": 10.0,
             "k_reduce": reduce_w, "reduced_solve": solve_w, "k_expand": 8.25}

@@ -16,16 +16,17 @@
 //   k_reduce   per 64x16 tile: coefficients of eq. 23 from the bathymetry, and
 //              the elimination of every 16-cell row segment and 16-cell column
 //              segment down to its first and last unknowns (partition
-//              method); writes the eliminated interior values in place and
-//              two reduced equations per segment.
+//              method); writes two reduced equations per segment (the
+//              eliminated interiors stay in LDS: the expansion redoes them).
 //   reduced    the reduced tridiagonal systems, by one of four strategies:
 //              k_pcr (parallel cyclic reduction, a workgroup per system),
 //              k_thomas (a lane per system), the factored sweeps with static
 //              factors (k_luw_solve: a workgroup per 64 systems held in
 //              registers; k_lu_solve: a lane per system) and the two-ended
 //              factored sweeps (k_lu2_solve).
-//   k_expand   per tile: back substitution of every segment from its solved
-//              end values, P = P^n + dP, Q = Q^n + dQ, shoreline fix (and the
+//   k_expand   per tile: every segment's elimination again (right-hand
+//              sides included) and back substitution from its solved end
+//              values, P = P^n + dP, Q = Q^n + dQ, shoreline fix (and the
 //              sponge after the last pass).
 // k_ghosts precomputes the wave-maker ghost values of one time level.
 #pragma once
@@ -356,7 +357,7 @@ __global__ __launch_bounds__(64 * SWG) __attribute__((amdgpu_waves_per_eu(4))) v
 // ------------------------------------------------------------- solver parts
 struct SolveArgs {
     Dom d;
-    float *rx, *ry;            // right-hand sides in, eliminated segment interiors out
+    float *rx, *ry;            // right-hand sides (read by the reduction and the expansion)
     float4 *redx, *redy;       // reduced equations (sub, diag, super, rhs) per unknown
     float *solx, *soly;        // reduced solutions
     // layout 1 (factored solve): the reduced right-hand sides (in the memory of
@@ -535,8 +536,13 @@ __device__ __forceinline__ void seg_eliminate(float *r, int st, float (&a)[M], f
     first = make_float4(a[0], b[0] - f * ah, -f * ch, r[0] - f * rh);
 }
 
-// Back substitution of one segment from its solved end values x0, xl; r holds
-// the eliminated interior values on entry and the solution on exit.
+// Solution of one segment from its solved end values x0, xl: the
+// elimination of seg_eliminate (the same operations in the same order, on
+// the right-hand sides too), then back substitution; r holds the right-hand
+// sides on entry and the solution on exit.  Redoing the right-hand-side
+// elimination here (one multiply-add a cell each way, next to the factors
+// this loop computes anyway) spares the reduction writing the eliminated
+// values to HBM and this kernel reading them back.
 template <int M>
 __device__ __forceinline__ void seg_expand(float *r, int st, float (&a)[M], float (&b)[M],
                                            const float (&c)[M], float x0, float xl) {
@@ -545,16 +551,18 @@ __device__ __forceinline__ void seg_expand(float *r, int st, float (&a)[M], floa
         const float f = a[k] * frcp(b[k - 1]);
         a[k] = -f * a[k - 1];
         b[k] = b[k] - f * c[k - 1];
+        r[k * st] = r[k * st] - f * r[(k - 1) * st];
     }
-    float ah = a[M - 2], bh = b[M - 2], ch = c[M - 2];
-    r[(M - 2) * st] = (r[(M - 2) * st] - ah * x0 - ch * xl) * frcp(bh);
+    float ah = a[M - 2], bh = b[M - 2], ch = c[M - 2], rh = r[(M - 2) * st];
+    r[(M - 2) * st] = (rh - ah * x0 - ch * xl) * frcp(bh);
 #pragma unroll
     for (int k = M - 3; k >= 1; --k) {
         const float f = c[k] * frcp(bh);
         ah = a[k] - f * ah;
         bh = b[k];
         ch = -f * ch;
-        r[k * st] = (r[k * st] - ah * x0 - ch * xl) * frcp(bh);
+        rh = r[k * st] - f * rh;
+        r[k * st] = (rh - ah * x0 - ch * xl) * frcp(bh);
     }
     r[0] = x0;
     r[(M - 1) * st] = xl;
@@ -605,13 +613,6 @@ __device__ __forceinline__ void reduce_body(const SolveArgs &A, SolveTile &s, in
             red[0] = first;
             red[1] = last;
         }
-    }
-    __syncthreads();
-    for (int k = tid; k < TX * TY; k += NT) {
-        const int cx = k % TX, cy = k / TX;
-        const size_t o = (size_t)(j0 + cy) * d.pitch + i0 + cx;
-        A.rx[o] = s.rx[cy][cx];
-        A.ry[o] = s.ry[cy][cx];
     }
 }
 
@@ -1131,8 +1132,9 @@ __device__ __forceinline__ void expand_body(const SolveArgs &A, SolveTile &s, in
             xl = sol[1];
         }
         float a[MX], b[MX], c[MX];
-        seg_coefs<MX>(A, s, i0, j0, 0, k0, row, a, b, c, nullptr, 1);
-        seg_expand<MX>(&s.rx[row][k0], 1, a, b, c, x0, xl);
+        float *r = &s.rx[row][k0];
+        seg_coefs<MX>(A, s, i0, j0, 0, k0, row, a, b, c, r, 1);  // boundary rows fold into r, as in the reduction
+        seg_expand<MX>(r, 1, a, b, c, x0, xl);
     } else if (tid < 128) {
         const int col = tid - 64;
         const int i = i0 + col;
@@ -1148,8 +1150,9 @@ __device__ __forceinline__ void expand_body(const SolveArgs &A, SolveTile &s, in
             xl = sol[1];
         }
         float a[TY], b[TY], c[TY];
-        seg_coefs<TY>(A, s, i0, j0, 1, col, 0, a, b, c, nullptr, TXP);
-        seg_expand<TY>(&s.ry[0][col], TXP, a, b, c, x0, xl);
+        float *r = &s.ry[0][col];
+        seg_coefs<TY>(A, s, i0, j0, 1, col, 0, a, b, c, r, TXP);
+        seg_expand<TY>(r, TXP, a, b, c, x0, xl);
     }
     __syncthreads();
     int bad = 0;
