@@ -208,7 +208,8 @@ def test_config4_full_size_batch_sampled_vs_alone():
 def test_snapshot_restore_continues_exactly():
     """A snapshot (state, history, edited bathymetry, step, time) restored
     into a fresh domain of the same grid continues bit for bit as the
-    original run; a snapshot of another grid is refused."""
+    original run; a snapshot of another grid is refused; the snapshot's
+    size equals the one ws_snapshot_bytes_grid gives for the grid."""
     ws = _ws()
     w = wl.config2(nx=160, ny=72, seed=9)
     say("case: snapshot / restore on %s" % w.name)
@@ -217,6 +218,7 @@ def test_snapshot_restore_continues_exactly():
     assert a.apply_edit(ws.EDIT_TERRAIN, 0.6 * w.nx * w.dx, 0.5 * w.ny * w.dy, 0.2, 5 * w.dx) == 0
     a.advance(5)
     snap = a.snapshot()
+    assert snap.numel() == ws.snapshot_bytes(a.g)   # the size a caller can budget before the domain exists
     a.advance(20)
     b = make(w)                                    # same grid and boundaries, fresh state
     b.advance(3)
