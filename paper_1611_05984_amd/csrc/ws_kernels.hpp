@@ -174,6 +174,10 @@ __device__ __forceinline__ void stencil_body(const StencilArgs &A, int bx, int b
     };
     load_row(j0 - 2);
 
+    // the corrector's row loop fully unrolled at 8 rows (no sliding-window
+    // moves; corrector 208 -> 198 us at 4096^2); the predictor, with more
+    // live history values, is faster rolled
+#pragma unroll(KIND == 2 && SYT <= 8 ? SYT + 4 : 1)
     for (int it = 0; it < SYT + 4; ++it) {
         const int r = j0 - 2 + it;
         e0 = e1; e1 = e2; e2 = e3; e3 = e4;
