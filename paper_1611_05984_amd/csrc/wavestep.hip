@@ -818,7 +818,6 @@ static dim3 strips_for(const ws_domain *d, int sy) {
     const int ns = (d->g.nx + SO - 1) / SO;
     return dim3((ns + SWG - 1) / SWG, (d->g.ny + sy - 1) / sy);
 }
-static dim3 strips(const ws_domain *d) { return strips_for(d, d->sy); }
 
 #define SY_SWITCH(K, sy, LAUNCH)                        \
     do {                                                \
@@ -1565,7 +1564,7 @@ extern "C" ws_status ws_tune(ws_domain *d, const char *cache_path, void *stream,
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     const int reps = 5;
-    float best_s = 1e30f, best_p = 1e30f;
+    float best_p = 1e30f;
     best.stencil_rows = SY;
     best.pcr_threads = PCR_NT;
     best.solver = WS_SOLVE_PCR;
@@ -1609,11 +1608,9 @@ extern "C" ws_status ws_tune(ws_domain *d, const char *cache_path, void *stream,
         if (t_rows[1][c] < t_rows[1][cc]) cc = c;
     }
     const float t_one = t_rows[0][one] + K * t_rows[1][one], t_two = t_rows[0][cp] + K * t_rows[1][cc];
-    best_s = t_one;
     best.stencil_rows = rows[one];
     best.corrector_rows = 0;
     if (K > 0 && cp != cc && t_two < 0.98f * t_one) {
-        best_s = t_two;
         best.stencil_rows = rows[cp];
         best.corrector_rows = rows[cc];
     }

@@ -130,7 +130,7 @@ __device__ __forceinline__ void stencil_body(const StencilArgs &A, int bx, int b
     const bool halo_lane = lane == 0 || lane == 63;
     const int j0 = by * SYT;
     const float th = d.theta, g = d.g, eps = d.eps;
-    const float rdx = d.rdx, rdy = d.rdy, Bd = d.Bd, B3 = d.Bd + 1.f / 3.f;
+    const float rdx = d.rdx, rdy = d.rdy, B3 = d.Bd + 1.f / 3.f;
     // strips whose cells and corners (with halo) all lie inside the domain
     // load without boundary handling
     const bool interior = c0 >= 1 && c0 + 64 <= d.nx - 1 && j0 >= 2 && j0 + SYT + 1 <= d.ny - 1;
@@ -177,7 +177,7 @@ __device__ __forceinline__ void stencil_body(const StencilArgs &A, int bx, int b
     // the corrector's row loop fully unrolled at 8 rows (no sliding-window
     // moves; corrector 208 -> 198 us at 4096^2); the predictor, with more
     // live history values, is faster rolled
-#pragma unroll(KIND == 2 && SYT <= 8 ? SYT + 4 : 1)
+#pragma unroll KIND == 2 && SYT <= 8 ? SYT + 4 : 1
     for (int it = 0; it < SYT + 4; ++it) {
         const int r = j0 - 2 + it;
         e0 = e1; e1 = e2; e2 = e3; e3 = e4;
