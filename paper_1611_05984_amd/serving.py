@@ -27,9 +27,10 @@ history and its step counter, so a session counts its steps from the
 checkpoint it was rolled back to (`base`).
 
 Reported: throughput, per-step latency seen by a session (tick wall time over
-the steps it made in that tick) at p50/p99, real-time ratio (simulated over
-wall time while resident; sessions still resident at the end count with their
-steps so far), queueing delay, and session counts.
+the steps it made in that tick) at p50/p99, real-time ratio (simulated time
+over wall time while resident; sessions still resident at the end count with
+their time so far), queueing delay, and session counts (done, failed,
+recovered, rollbacks).
 """
 from __future__ import annotations
 
