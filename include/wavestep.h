@@ -76,7 +76,7 @@ enum { WS_READ_W = 0, WS_READ_H = 1 };                           /* first field 
 typedef struct {
     int32_t nx, ny;          /* cells, >= 2 each; five padded fields (nx rounded  */
                              /* up to 64, ny to 16, 4 B a cell) must stay under   */
-                             /* 4 GiB: about 2.1e8 cells (e.g. 14592 x 14592)     */
+                             /* 4 GiB: about 2.1e8 cells (squares up to 14640^2)  */
     int32_t n_corr;          /* corrector passes per step [2]                     */
     int32_t model;           /* WS_BSNQ or WS_NLSW [WS_BSNQ]                      */
     int32_t friction;        /* WS_FRIC_* [WS_FRIC_NONE]                          */

@@ -102,7 +102,7 @@ struct Layout {
 
 // The stencil addresses the fields of a group (up to five, one field stride
 // apart) by 32-bit byte offsets from the group's base: five padded fields
-// must span less than 4 GiB (about 2.1e8 cells, e.g. 14592 x 14592).
+// must span less than 4 GiB (about 2.1e8 cells; squares up to 14640 x 14640).
 static bool offsets_fit(const ws_grid *g) {
     if (g->nx > (1 << 20) || g->ny > (1 << 20)) return false;
     const size_t field = align256(sizeof(float) * (size_t)roundup(g->ny, TY) * (size_t)roundup(g->nx, TX));

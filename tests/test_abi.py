@@ -39,6 +39,8 @@ def test_defaults_and_workspace_sizing():
     assert ws.workspace_bytes(ws.grid(64, 64, 0.1, 0.1, 0.01, theta=2.5)) == 0
     # the stencil's 32-bit field offsets: five padded fields under 4 GiB
     assert ws.workspace_bytes(ws.grid(14592, 14592, 0.1, 0.1, 0.01)) > 0
+    assert ws.workspace_bytes(ws.grid(14640, 14640, 0.1, 0.1, 0.01)) > 0     # the largest square
+    assert ws.workspace_bytes(ws.grid(14641, 14641, 0.1, 0.1, 0.01)) == 0
     assert ws.workspace_bytes(ws.grid(14592, 14720, 0.1, 0.1, 0.01)) == 0
     assert ws.workspace_bytes(ws.grid(16384, 16384, 0.1, 0.1, 0.01)) == 0
     assert ws.workspace_bytes(ws.grid(2, 1 << 21, 0.1, 0.1, 0.01)) == 0

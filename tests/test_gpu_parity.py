@@ -415,3 +415,54 @@ def test_config3_full_size_parity_and_rest():
     gpu.advance(3)
     ora.advance(3)
     check(gpu, ora, 1.0, 30.0, rel=1e-5, what="config3 step 3")
+
+
+def test_maximum_grid_transposition_symmetry():
+    """The largest square grid the library accepts (14640 x 14640, 2.1e8
+    cells, ragged against the 64-column tiles: five padded fields just under
+    4 GiB, the limit of the stencil's 32-bit field offsets) runs every kernel
+    at its largest offsets.  Two
+    water humps mirrored across the diagonal, one where offsets are small
+    (top right) and one where they are largest (bottom left), over a
+    transposition-symmetric bed: after 40 steps eta(i, j) = eta(j, i) and
+    P(i, j) = Q(j, i) to FP32 rounding, far from both humps the lake is
+    still exactly at rest, and the volume is conserved.  An access that went
+    wrong with the offset would break the symmetry by O(1)."""
+    ws = _ws()
+    n, dx, depth, amp = 14640, 1.0, 2.0, 0.1
+    assert ws.workspace_bytes(ws.grid(n, n, dx, dx, 0.01)) > 0
+    assert ws.workspace_bytes(ws.grid(n + 1, n + 1, dx, dx, 0.01)) == 0   # the next square is refused
+    dt = wl.courant_dt(0.2, dx, depth)
+    c = (np.arange(n + 1) - n / 2) * dx
+    r2 = c[:, None] ** 2 + c[None, :] ** 2
+    z = (-depth + 0.5 * np.exp(-r2 / (2 * (200 * dx) ** 2))).astype(np.float32)  # symmetric mound
+    say("case: maximum grid %dx%d (workspace %.1f GB)" % (n, n, ws.workspace_bytes(ws.grid(n, n, dx, dx, dt)) / 1e9))
+    d = ws.Domain(n, n, dx, dx, dt, z)
+    del z, c, r2
+    d.set_tuning(8, 256, ws.SOLVE_LU)
+    lo, hi = 0.1 * n * dx, 0.9 * n * dx
+    assert d.apply_edit(ws.EDIT_WATER, hi, lo, amp, 20 * dx) == 0   # x large, y small: small offsets
+    assert d.apply_edit(ws.EDIT_WATER, lo, hi, amp, 20 * dx) == 0   # x small, y large: largest offsets
+    w0, _, _ = d.state_numpy()
+    v0 = float(np.sum(w0, dtype=np.float64))
+    del w0
+    d.advance(40)
+    step, _, health = d.query()
+    say("  40 steps done: step %d health %d" % (step, health))
+    assert step == 40 and health == 0
+    w, P, Q = d.state_numpy()
+    d.close()
+    assert np.isfinite(w).all() and np.isfinite(P).all() and np.isfinite(Q).all()
+    cpq = amp * math.sqrt(9.81 * depth)
+    dw = float(np.max(np.abs(w - w.T)))
+    dpq = float(np.max(np.abs(P - Q.T)))
+    say("  max |eta - eta^T| = %.3e, max |P - Q^T| = %.3e, max eta = %.3e" % (dw, dpq, float(w.max())))
+    assert float(w.max()) > 0.1 * amp                 # the humps are still there
+    assert dw <= 1e-4 * amp and dpq <= 1e-4 * cpq
+    # the waves travel about 8 m in 40 steps: the middle of the basin is at rest, exactly
+    m = n // 2
+    assert not np.any(w[m - 1000:m + 1000, m - 1000:m + 1000])
+    assert not np.any(P[m - 1000:m + 1000, m - 1000:m + 1000]) and not np.any(Q[m - 1000:m + 1000, m - 1000:m + 1000])
+    v1 = float(np.sum(w, dtype=np.float64))
+    say("  volume change %.3e of %.3e" % (v1 - v0, v0))
+    assert abs(v1 - v0) <= 1e-4 * abs(v0)
