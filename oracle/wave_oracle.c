@@ -19,7 +19,8 @@
  * every side (sec. 2.4).  Bathymetry z is sampled at cell corners (i dx, j dy)
  * and is continuous and bilinear, as the central-upwind scheme (KP07) it
  * follows assumes; the paper does not say how its bathymetry texture is
- * sampled (reading, see the design notes).
+ * sampled, so this corner sampling is a reading of the paper, not its
+ * statement.
  *
  * Parity pins live in tests/ (lake at rest, volume, solitary wave, linear
  * dispersion relation, dam breaks, symmetries, polynomial exactness,
