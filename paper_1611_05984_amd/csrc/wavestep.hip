@@ -814,8 +814,11 @@ extern "C" ws_status ws_apply_edit(ws_domain *d, int32_t kind, double x0, double
     return WS_OK;
 }
 
-static dim3 strips_for(const ws_domain *d, int sy) {
+// Stencil workgroup grid: SWG side-by-side strips of sy rows per workgroup,
+// or (stack) one strip of SWG stacked blocks of sy rows.
+static dim3 strips_for(const ws_domain *d, int sy, bool stack = false) {
     const int ns = (d->g.nx + SO - 1) / SO;
+    if (stack) return dim3(ns, (d->g.ny + sy * SWG - 1) / (sy * SWG));
     return dim3((ns + SWG - 1) / SWG, (d->g.ny + sy - 1) / sy);
 }
 
@@ -829,7 +832,10 @@ static dim3 strips_for(const ws_domain *d, int sy) {
         else LAUNCH(K<32>);                             \
     } while (0)
 
-static void launch_stencil(int sy, dim3 grid, hipStream_t st, const StencilArgs &sa) {
+// The workgroup grid follows the kernel's layout: the corrector's waves are
+// stacked, the predictors' side by side.
+static void launch_stencil(const ws_domain *d, int sy, hipStream_t st, const StencilArgs &sa) {
+    const dim3 grid = strips_for(d, sy, sa.kind == 2);
     const dim3 g1(grid.x * grid.y);  // 1-D grid in XCD-aware tile order
     const int gx = (int)grid.x;
 #define L3(KERN) hipLaunchKernelGGL(KERN, g1, dim3(64 * SWG), 0, st, sa, gx)
@@ -1005,7 +1011,7 @@ static ws_status run_pass(ws_domain *d, const StencilArgs &sa, const SolveArgs &
     {
         ProfScope p(d, st, sa.kind == 2 ? WS_K_CORRECTOR : WS_K_PREDICTOR);
         const int rows = sa.kind == 2 && d->syc ? d->syc : d->sy;
-        launch_stencil(rows, strips_for(d, rows), st, sa);
+        launch_stencil(d, rows, st, sa);
     }
     if (!so.nlsw) {  // NLSW: identity systems, nothing to solve
         {
@@ -1582,15 +1588,14 @@ extern "C" ws_status ws_tune(ws_domain *d, const char *cache_path, void *stream,
     float t_rows[2][6];
     for (int c = 0; c < 6; ++c) t_rows[0][c] = t_rows[1][c] = 1e30f;
     for (int c = 0; c < 6; ++c) {  // warm-up
-        launch_stencil(rows[c], strips_for(d, rows[c]), st, sp);
-        launch_stencil(rows[c], strips_for(d, rows[c]), st, sa);
+        launch_stencil(d, rows[c], st, sp);
+        launch_stencil(d, rows[c], st, sa);
     }
     for (int round = 0; round < 3; ++round)
         for (int kind = 0; kind < 2; ++kind)
             for (int c = 0; c < 6; ++c) {
-                const dim3 grid = strips_for(d, rows[c]);
                 HIPCHK(hipEventRecord(e0, st));
-                for (int k = 0; k < reps; ++k) launch_stencil(rows[c], grid, st, kind ? sa : sp);
+                for (int k = 0; k < reps; ++k) launch_stencil(d, rows[c], st, kind ? sa : sp);
                 HIPCHK(hipEventRecord(e1, st));
                 HIPCHK(hipEventSynchronize(e1));
                 float ms = 0.f;
