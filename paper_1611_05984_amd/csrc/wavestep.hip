@@ -815,11 +815,10 @@ extern "C" ws_status ws_apply_edit(ws_domain *d, int32_t kind, double x0, double
 }
 
 // Stencil workgroup grid: SWG side-by-side strips of sy rows per workgroup,
-// or (stack) one strip of SWG stacked blocks of sy rows.
-static dim3 strips_for(const ws_domain *d, int sy, bool stack = false) {
+// or (solo) one strip per workgroup.
+static dim3 strips_for(const ws_domain *d, int sy, bool solo = false) {
     const int ns = (d->g.nx + SO - 1) / SO;
-    if (stack) return dim3(ns, (d->g.ny + sy * SWG - 1) / (sy * SWG));
-    return dim3((ns + SWG - 1) / SWG, (d->g.ny + sy - 1) / sy);
+    return dim3(solo ? ns : (ns + SWG - 1) / SWG, (d->g.ny + sy - 1) / sy);
 }
 
 #define SY_SWITCH(K, sy, LAUNCH)                        \
@@ -832,13 +831,14 @@ static dim3 strips_for(const ws_domain *d, int sy, bool stack = false) {
         else LAUNCH(K<32>);                             \
     } while (0)
 
-// The workgroup grid follows the kernel's layout: the corrector's waves are
-// stacked, the predictors' side by side.
+// The workgroup shape follows the kernel: the corrector runs one-wave
+// workgroups, the predictors SWG strips a workgroup.
 static void launch_stencil(const ws_domain *d, int sy, hipStream_t st, const StencilArgs &sa) {
-    const dim3 grid = strips_for(d, sy, sa.kind == 2);
+    const bool solo = sa.kind == 2;
+    const dim3 grid = strips_for(d, sy, solo);
     const dim3 g1(grid.x * grid.y);  // 1-D grid in XCD-aware tile order
     const int gx = (int)grid.x;
-#define L3(KERN) hipLaunchKernelGGL(KERN, g1, dim3(64 * SWG), 0, st, sa, gx)
+#define L3(KERN) hipLaunchKernelGGL(KERN, g1, dim3(solo ? 64 : 64 * SWG), 0, st, sa, gx)
     if (sa.kind == 2) SY_SWITCH(k_stencil_c, sy, L3);
     else if (sa.kind == 1) SY_SWITCH(k_stencil_p, sy, L3);
     else SY_SWITCH(k_stencil_e, sy, L3);
