@@ -1189,6 +1189,7 @@ static BatchDesc make_desc(const ws_domain *d, int sy) {
     const dim3 sg = strips_for(d, sy);
     D.sgx = (int)sg.x;
     D.sgy = (int)sg.y;
+    D.sgxc = (int)strips_for(d, sy, true).x;
     D.tgx = d->nxp / TX;
     D.tgy = d->nyp / TY;
     D.nsys = d->g.ny + d->g.nx;
@@ -1270,7 +1271,7 @@ static ws_status batch_upload(ws_batch *b) {
         const BatchDesc &D = desc[k];
         pre[0][k + 1] = pre[0][k] + D.sgx * D.sgy;
         pre[1][k + 1] = pre[1][k] + D.tgx * D.tgy;
-        const dim3 sgc = strips_for(d, b->syc ? b->syc : b->sy);
+        const dim3 sgc = strips_for(d, b->syc ? b->syc : b->sy, true);  // the corrector's one-wave grid
         pre[4][k + 1] = pre[4][k] + (int)(sgc.x * sgc.y);
         pre[2][k + 1] = pre[2][k] + (b->solver == WS_SOLVE_LU2                     ? solve2_waves(D.d.nx, D.d.ny)
                                      : b->solver == WS_SOLVE_LU && luw_waves(nred) ? luw_groups(D.d.nx, D.d.ny)
@@ -1305,9 +1306,9 @@ static ws_status batch_step(ws_batch *b, hipStream_t st) {
     }
     for (int p = 0; p <= b->maxK; ++p) {
         // predictor pass: stencil_rows; corrector passes: their own height
-        const int q = p > 0 && b->syc ? 4 : 0, rows = q ? b->syc : b->sy;
+        const int q = p > 0 ? 4 : 0, rows = p > 0 && b->syc ? b->syc : b->sy;
         const dim3 sg(b->total[q]), pg(b->total[2]);
-#define L4(KERN) hipLaunchKernelGGL(KERN, sg, dim3(64 * SWG), 0, st, b->d_desc, b->d_state, b->d_pre[q], n, p)
+#define L4(KERN) hipLaunchKernelGGL(KERN, sg, dim3(p > 0 ? 64 : 64 * SWG), 0, st, b->d_desc, b->d_state, b->d_pre[q], n, p)
         if (p > 0) SY_SWITCH(kb_stencil_c, rows, L4);
         else {
             SY_SWITCH(kb_stencil_e, rows, L4);
@@ -1751,8 +1752,8 @@ extern "C" ws_status ws_batch_tune(ws_batch *b, void *stream, ws_tuning *out) {
         float ms[2];
         for (int p = 0; p < 2; ++p)
             ms[p] = time_it([&] {
-                const dim3 sg(b->total[0]);
-#define L5(KERN) hipLaunchKernelGGL(KERN, sg, dim3(64 * SWG), 0, st, b->d_desc, b->d_state, b->d_pre[0], n, p)
+                const dim3 sg(b->total[p > 0 ? 4 : 0]);
+#define L5(KERN) hipLaunchKernelGGL(KERN, sg, dim3(p > 0 ? 64 : 64 * SWG), 0, st, b->d_desc, b->d_state, b->d_pre[p > 0 ? 4 : 0], n, p)
                 if (p > 0) SY_SWITCH(kb_stencil_c, b->sy, L5);
                 else SY_SWITCH(kb_stencil_p, b->sy, L5);
 #undef L5

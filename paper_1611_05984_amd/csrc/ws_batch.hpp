@@ -31,7 +31,7 @@ struct BatchDesc {
     int tgx, tgy;              // solver tile grid
     int nsys;                  // reduced systems: ny + nx
     int makers;                // number of wave-maker sides
-    int pad;
+    int sgxc;                  // corrector stencil grid width (one-wave workgroups: the strip count)
     const int *health;         // the domain's health word
 };
 
@@ -97,7 +97,10 @@ __device__ __forceinline__ void kb_stencil_body(const BatchDesc *__restrict__ de
     if (v < 0) return;
     const int local = b - prefix[dm];
     const StencilArgs A = load_params(D.sa + v);
-    stencil_body<SYT, KIND>(A, local % D.sgx, local / D.sgx);
+    if constexpr (KIND == 2)  // one-wave workgroups, as the single-domain corrector
+        stencil_body<SYT, 2, true>(A, local % D.sgxc, local / D.sgxc);
+    else
+        stencil_body<SYT, KIND>(A, local % D.sgx, local / D.sgx);
 }
 template <int SYT>
 __global__ __launch_bounds__(64 * SWG) __attribute__((amdgpu_waves_per_eu(4))) void kb_stencil_e(const BatchDesc *__restrict__ descs,
@@ -112,7 +115,7 @@ __global__ __launch_bounds__(64 * SWG) __attribute__((amdgpu_waves_per_eu(4))) v
     kb_stencil_body<SYT, 1>(descs, states, prefix, ndom, p);
 }
 template <int SYT>
-__global__ __launch_bounds__(64 * SWG) __attribute__((amdgpu_waves_per_eu(4))) void kb_stencil_c(const BatchDesc *__restrict__ descs,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void kb_stencil_c(const BatchDesc *__restrict__ descs,
                                                          const BatchState *__restrict__ states,
                                                          const int *__restrict__ prefix, int ndom, int p) {
     kb_stencil_body<SYT, 2>(descs, states, prefix, ndom, p);
