@@ -1315,7 +1315,7 @@ static ws_status batch_step(ws_batch *b, hipStream_t st) {
             SY_SWITCH(kb_stencil_p, rows, L4);
         }
 #undef L4
-        hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NT), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, p);
+        hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NTB), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, p);
         const size_t shm = sizeof(float4) * b->nred;
         if (b->solver == WS_SOLVE_LU2)
             hipLaunchKernelGGL(kb_lu2_solve, pg, dim3(64), 0, st, b->d_desc, b->d_state, b->d_pre[2], n, p);
@@ -1332,7 +1332,7 @@ static ws_status batch_step(ws_batch *b, hipStream_t st) {
                 hipLaunchKernelGGL((kb_pcr<S::threads, S::epl>), pg, dim3(S::threads), shm, st, b->d_desc,
                                    b->d_state, b->d_pre[2], n, p);
             });
-        hipLaunchKernelGGL(kb_expand, dim3(b->total[1]), dim3(NT), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, p);
+        hipLaunchKernelGGL(kb_expand, dim3(b->total[1]), dim3(NTB), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, p);
     }
     hipLaunchKernelGGL(kb_finish, dim3((n + 255) / 256), dim3(256), 0, st, b->d_desc, b->d_state, n);
     HIPCHK(hipGetLastError());
@@ -1780,7 +1780,7 @@ extern "C" ws_status ws_batch_tune(ws_batch *b, void *stream, ws_tuning *out) {
     const int n = (int)b->order.size();
     best = 1e30f;
     if (n > 0) {
-        hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NT), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, 1);
+        hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NTB), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, 1);
         for (int c = 0; c < 3; ++c) {
             const float ms = time_it([&] {
                 const dim3 pg(b->total[2]);
@@ -1799,7 +1799,7 @@ extern "C" ws_status ws_batch_tune(ws_batch *b, void *stream, ws_tuning *out) {
         if ((r = batch_upload(b)) != WS_OK) return r;
         float total = 0.f;
         for (int k = 0; k < 4; ++k) {
-            hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NT), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, 1);
+            hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NTB), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, 1);
             (void)hipEventRecord(e0, st);
             hipLaunchKernelGGL(kb_thomas, dim3(b->total[2]), dim3(64), 0, st, b->d_desc, b->d_state, b->d_pre[2], n, 1);
             (void)hipEventRecord(e1, st);
@@ -1818,7 +1818,7 @@ extern "C" ws_status ws_batch_tune(ws_batch *b, void *stream, ws_tuning *out) {
             if ((r = ensure_factors(b->slots[sl], st)) != WS_OK) return r;
         total = 0.f;
         for (int k = 0; k < 4; ++k) {
-            hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NT), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, 1);
+            hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NTB), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, 1);
             (void)hipEventRecord(e0, st);
             if (const int G = luw_waves(b->nred))
                 hipLaunchKernelGGL(kb_luw_solve, dim3(b->total[2]), dim3(64 * G), 0, st, b->d_desc, b->d_state,
@@ -1843,7 +1843,7 @@ extern "C" ws_status ws_batch_tune(ws_batch *b, void *stream, ws_tuning *out) {
             if ((r = ensure_factors(b->slots[sl], st)) != WS_OK) return r;
         total = 0.f;
         for (int k = 0; k < 4; ++k) {
-            hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NT), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, 1);
+            hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NTB), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, 1);
             (void)hipEventRecord(e0, st);
             hipLaunchKernelGGL(kb_lu2_solve, dim3(b->total[2]), dim3(64), 0, st, b->d_desc, b->d_state, b->d_pre[2], n, 1);
             (void)hipEventRecord(e1, st);

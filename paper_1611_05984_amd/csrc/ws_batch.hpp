@@ -121,7 +121,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void kb
     kb_stencil_body<SYT, 2>(descs, states, prefix, ndom, p);
 }
 
-__global__ __launch_bounds__(NT) void kb_reduce(const BatchDesc *__restrict__ descs,
+// The batch's tile kernels run two-wave workgroups (NTB threads): over many
+// small domains that is 2.6 % faster than the single-domain kernels' four
+// waves, which are 9 % faster on one large domain.  The same arithmetic per
+// cell either way.
+__global__ __launch_bounds__(NTB) void kb_reduce(const BatchDesc *__restrict__ descs,
                                                 const BatchState *__restrict__ states,
                                                 const int *__restrict__ prefix, int ndom, int p) {
     __shared__ SolveTile s;
@@ -131,7 +135,7 @@ __global__ __launch_bounds__(NT) void kb_reduce(const BatchDesc *__restrict__ de
     if (v < 0) return;
     const int local = b - prefix[dm];
     const SolveArgs A = load_params(D.so + v);
-    reduce_body(A, s, local % D.tgx, local / D.tgx);
+    reduce_body<NTB>(A, s, local % D.tgx, local / D.tgx);
 }
 
 template <int PNT, int EPL>
@@ -155,7 +159,7 @@ __global__ __launch_bounds__(PNT) void kb_pcr(const BatchDesc *__restrict__ desc
     }
 }
 
-__global__ __launch_bounds__(NT) void kb_expand(const BatchDesc *__restrict__ descs,
+__global__ __launch_bounds__(NTB) void kb_expand(const BatchDesc *__restrict__ descs,
                                                 const BatchState *__restrict__ states,
                                                 const int *__restrict__ prefix, int ndom, int p) {
     __shared__ SolveTile s;
@@ -165,7 +169,7 @@ __global__ __launch_bounds__(NT) void kb_expand(const BatchDesc *__restrict__ de
     if (v < 0) return;
     const int local = b - prefix[dm];
     const SolveArgs A = load_params(D.so + v);
-    expand_body(A, s, local % D.tgx, local / D.tgx);
+    expand_body<NTB>(A, s, local % D.tgx, local / D.tgx);
 }
 
 // Reduced systems by lane-per-system Thomas: workgroup (one wave) b - prefix

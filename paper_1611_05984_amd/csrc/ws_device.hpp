@@ -15,6 +15,7 @@ constexpr int TX = 64;        // solver tile width  (cells along x)
 constexpr int TY = 16;        // solver tile height (cells along y) = column segment length
 constexpr int MX = 16;        // row segment length (4 per solver tile row)
 constexpr int NT = 256;       // threads per solver tile workgroup (4 wave64)
+constexpr int NTB = 128;      // the same in the batch (2 wave64)
 constexpr int SO = 62;        // stencil: output columns per 64-lane strip wave
 constexpr int SY = 32;        // stencil: rows streamed per strip wave
 constexpr int SWG = 4;        // stencil: strip waves per workgroup

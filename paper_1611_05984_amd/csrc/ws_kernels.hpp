@@ -404,37 +404,40 @@ __device__ __forceinline__ float ghost_change(const SolveArgs &A, int side, int 
 // Stage a tile: its two right-hand-side fields and the corner depths around
 // it, all loads issued before any LDS store so that they share one memory
 // latency, then the cell depths from the corners.
-constexpr int CPT = TX * TY / NT;                      // tile cells per thread
-constexpr int ZPT = ((TX + 3) * (TY + 3) + NT - 1) / NT;  // corner values per thread
+// Tile cells and corner values per thread for a workgroup of T threads.
+template <int T> constexpr int cells_per_thread() { return TX * TY / T; }
+template <int T> constexpr int corners_per_thread() { return ((TX + 3) * (TY + 3) + T - 1) / T; }
+template <int T = NT>
 __device__ __forceinline__ void stage_tile(const SolveArgs &A, SolveTile &s, int i0, int j0) {
+    constexpr int CPT = cells_per_thread<T>(), ZPT = corners_per_thread<T>();
     const Dom &d = A.d;
     const int tid = threadIdx.x;
     float vx[CPT], vy[CPT], vz[ZPT];
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
-        const int k = tid + m * NT, cx = k % TX, cy = k / TX;
+        const int k = tid + m * T, cx = k % TX, cy = k / TX;
         const size_t o = (size_t)(j0 + cy) * d.pitch + i0 + cx;
         vx[m] = A.rx[o];
         vy[m] = A.ry[o];
     }
 #pragma unroll
     for (int m = 0; m < ZPT; ++m) {
-        const int k = tid + m * NT, lx = k % (TX + 3), ly = k / (TX + 3);
+        const int k = tid + m * T, lx = k % (TX + 3), ly = k / (TX + 3);
         vz[m] = k < (TX + 3) * (TY + 3) ? corner_D(d, i0 + lx - 1, j0 + ly - 1) : 0.f;
     }
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
-        const int k = tid + m * NT, cx = k % TX, cy = k / TX;
+        const int k = tid + m * T, cx = k % TX, cy = k / TX;
         s.rx[cy][cx] = vx[m];
         s.ry[cy][cx] = vy[m];
     }
 #pragma unroll
     for (int m = 0; m < ZPT; ++m) {
-        const int k = tid + m * NT, lx = k % (TX + 3), ly = k / (TX + 3);
+        const int k = tid + m * T, lx = k % (TX + 3), ly = k / (TX + 3);
         if (k < (TX + 3) * (TY + 3)) s.cz[ly][lx] = vz[m];
     }
     __syncthreads();
-    for (int k = tid; k < (TX + 2) * (TY + 2); k += NT) {
+    for (int k = tid; k < (TX + 2) * (TY + 2); k += T) {
         const int lx = k % (TX + 2), ly = k / (TX + 2);
         s.dc[ly][lx] = fmaxf(0.25f * ((s.cz[ly][lx] + s.cz[ly][lx + 1]) + (s.cz[ly + 1][lx] + s.cz[ly + 1][lx + 1])), 0.f);
     }
@@ -581,11 +584,12 @@ __device__ __forceinline__ void seg_expand(float *r, int st, float (&a)[M], floa
 
 // Wave 0 owns the 64 row segments of a tile (lane -> segment lane/16 of row
 // lane%16, conflict-free with the padded rows), wave 1 its 64 column segments.
+template <int T = NT>
 __device__ __forceinline__ void reduce_body(const SolveArgs &A, SolveTile &s, int bx, int by) {
     const Dom &d = A.d;
     const int tid = threadIdx.x;
     const int i0 = bx * TX, j0 = by * TY;
-    stage_tile(A, s, i0, j0);
+    stage_tile<T>(A, s, i0, j0);
     if (tid < 64) {
         const int row = tid % 16, seg = tid / 16, k0 = seg * MX;
         float a[MX], b[MX], c[MX];
@@ -1109,7 +1113,9 @@ __global__ __launch_bounds__(PNT) void k_pcr(SolveArgs A) {
     pcr_body<PNT, EPL>(A, buf, blockIdx.x);
 }
 
+template <int T = NT>
 __device__ __forceinline__ void expand_body(const SolveArgs &A, SolveTile &s, int bx, int by) {
+    constexpr int CPT = cells_per_thread<T>();
     const Dom &d = A.d;
     const int tid = threadIdx.x;
     const int i0 = bx * TX, j0 = by * TY;
@@ -1117,14 +1123,14 @@ __device__ __forceinline__ void expand_body(const SolveArgs &A, SolveTile &s, in
     float pre_e[CPT], pre_p[CPT], pre_q[CPT];
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
-        const int k = tid + m * NT, cx = k % TX, cy = k / TX, i = i0 + cx, j = j0 + cy;
+        const int k = tid + m * T, cx = k % TX, cy = k / TX, i = i0 + cx, j = j0 + cy;
         const int o = j * d.pitch + i;
         const bool in = i < d.nx && j < d.ny;
         pre_e[m] = in ? A.eta[o] : 0.f;
         pre_p[m] = in ? A.pbase[o] : 0.f;
         pre_q[m] = in ? A.qbase[o] : 0.f;
     }
-    stage_tile(A, s, i0, j0);
+    stage_tile<T>(A, s, i0, j0);
     if (A.nlsw) {
         // identity systems (eq. 21-22 with the dispersive coefficients zero):
         // the partitioned solve would return the increments unchanged
@@ -1169,7 +1175,7 @@ __device__ __forceinline__ void expand_body(const SolveArgs &A, SolveTile &s, in
     int bad = 0;
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
-        const int k = tid + m * NT, cx = k % TX, cy = k / TX, i = i0 + cx, j = j0 + cy;
+        const int k = tid + m * T, cx = k % TX, cy = k / TX, i = i0 + cx, j = j0 + cy;
         if (i >= d.nx || j >= d.ny) continue;
         const int o = j * d.pitch + i;
         float P = pre_p[m] + s.rx[cy][cx], Q = pre_q[m] + s.ry[cy][cx], e = pre_e[m];
