@@ -61,6 +61,8 @@ def lib():
         L.or_get_time.argtypes = [C.c_void_p]
         L.or_diag_dominant.argtypes = [C.c_void_p]
         L.or_eval_rhs.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_double] + [_dp] * 7
+        L.or_set_clock.argtypes = [C.c_void_p, C.c_int64, C.c_double]
+        L.or_set_history.argtypes = [C.c_void_p, C.c_int] + [_dp] * 5
         L.or_eval_solve.argtypes = [C.c_void_p, _dp, _dp, C.c_double, _dp, _dp]
         L.or_thomas.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp]
         L.or_eckart_k.restype = C.c_double
@@ -194,6 +196,21 @@ class Domain:
 
     def diag_dominant(self):
         return bool(lib().or_diag_dominant(self._h))
+
+    def set_clock(self, step, t):
+        """Set the count of completed steps and the time (test access)."""
+        if lib().or_set_clock(self._h, int(step), float(t)):
+            raise ValueError("oracle: bad step count")
+
+    def set_history(self, lag, E, F, G, Fs=None, Gs=None):
+        """Load the right-hand side of level n-lag (lag 1 or 2, relative to
+        the next step) into the multistep history (test access); arrays of
+        shape (ny, nx), None for zeros."""
+        n = self.nx * self.ny
+        z = np.zeros(n)
+        arrs = [z if a is None else _f64(a, n) for a in (E, F, G, Fs, Gs)]
+        if lib().or_set_history(self._h, int(lag), *arrs):
+            raise ValueError("oracle: bad history lag")
 
     def eval_rhs(self, w, P, Q, t=0.0):
         """(E, F, G, F*, G*, U*, V*) of an interior state, ghosts at time t."""

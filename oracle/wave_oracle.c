@@ -1105,6 +1105,33 @@ int or_eval_rhs(or_domain *D, const double *w, const double *P, const double *Q,
     return 0;
 }
 
+/* Set the number of completed steps and the time.  Together with
+ * or_set_history it lets a step start from a known multistep history instead
+ * of the Euler start-up of sec. 2.3 (steps 1 and 2 after a start). */
+int or_set_clock(or_domain *D, int64_t step, double t) {
+    if (step < 0) return -1;
+    D->step = step;
+    D->t = t;
+    return 0;
+}
+
+/* Load the right-hand side (E, F, G, F*, G*) of an earlier time level into
+ * the multistep history ring: lag 1 is level n-1 and lag 2 level n-2 with
+ * respect to the next step (whose own level n its predictor computes).
+ * Arrays are interior, row-major nx*ny; a NULL array loads zeros. */
+int or_set_history(or_domain *D, int lag, const double *E, const double *F, const double *G,
+                   const double *Fs, const double *Gs) {
+    if (lag < 1 || lag > 2) return -1;
+    const int slot = (int)(((D->step - lag) % 3 + 3) % 3);
+    const double *src[5] = {E, F, G, Fs, Gs};
+    double *dst[5] = {D->E[slot], D->F[slot], D->G[slot], D->Fs[slot], D->Gs[slot]};
+    for (int f = 0; f < 5; ++f)
+        for (int j = 0; j < D->p.ny; ++j)
+            for (int i = 0; i < D->p.nx; ++i)
+                dst[f][CI(D, i, j)] = src[f] ? src[f][(size_t)j * D->p.nx + i] : 0.0;
+    return 0;
+}
+
 /* Solve the row systems (21) and column systems (22) for right-hand sides
  * U, V (interior, row-major) with wave-maker ghosts at time t. */
 int or_eval_solve(or_domain *D, const double *U, const double *V, double t, double *P, double *Q) {
