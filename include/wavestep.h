@@ -136,6 +136,27 @@ ws_status ws_domain_init(const ws_grid *g, const float *z_corners_dev, void *wor
 
 ws_status ws_domain_destroy(ws_domain *d);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc: work being captured into a graph elsewhere, tight serving loops,
+ * harnesses that forbid allocation).  The same as ws_domain_init, except that
+ * the workspace is the library's own static device array of
+ * WS_STATIC_WORKSPACE_BYTES (80 MiB: grids up to 1024 x 512 cells, about
+ * 6.9e5 cells of any shape), one per GPU, held from the library's first use
+ * on that GPU until the process ends, and that the handle lives in static
+ * storage: the call allocates nothing, on the device or on the host.  It
+ * uses the array of the device current at the call (`stream` must belong to
+ * it).  The array is cleared at every such init (a destroyed domain's
+ * contents do not carry over).  One such domain per device at a time:
+ * WS_EBUSY while another one on the same device is alive (ws_domain_destroy
+ * releases the array); WS_ENOMEM, with the sizes in ws_last_error(), if the
+ * grid needs more than the array holds.  Every other call works on the
+ * returned handle as on any domain.  Work on two such domains of one device
+ * cannot overlap, since there is only one; two threads calling this on one
+ * device race for the array, and the second gets WS_EBUSY.  Synchronous. */
+#define WS_STATIC_WORKSPACE_BYTES ((size_t)80 << 20)
+ws_status ws_domain_init_static(const ws_grid *g, const float *z_corners_dev, void *stream,
+                                ws_domain **out);
+
 /* Boundary condition of one side (WS_WEST..WS_NORTH).  Synchronous. */
 ws_status ws_set_boundary(ws_domain *d, int32_t side, const ws_boundary *b);
 

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -83,6 +84,7 @@ struct ws_domain {
     int last_corr;                 // correctors the last step ran
     int64_t total_corr;            // correctors since the tolerance was set
     double last_dw, last_dpq;      // changes measured after the last corrector
+    int static_dev;                // device whose static array holds the workspace (-1: the caller's)
 };
 
 static ws_status busy_check(const ws_domain *d, const char *who) {
@@ -406,19 +408,26 @@ __global__ void k_sponge(Dom d, float *e, float *P, float *Q) {
 }
 
 // ------------------------------------------------------------------ API
-extern "C" ws_status ws_domain_init(const ws_grid *g, const float *z_corners_dev, void *workspace_dev,
-                                    size_t workspace_bytes, void *stream, ws_domain **out) {
-    if (!out) return fail(WS_EINVAL, "ws_domain_init: out is NULL");
-    *out = nullptr;
-    if (!grid_ok(g)) return fail(WS_EINVAL, "ws_domain_init: invalid grid parameters");
-    if (!z_corners_dev || !workspace_dev) return fail(WS_EINVAL, "ws_domain_init: NULL device pointer");
-    if (((uintptr_t)workspace_dev & 255) != 0) return fail(WS_EINVAL, "ws_domain_init: workspace not 256-byte aligned");
+// Argument checks shared by both ways of creating a domain.
+static ws_status init_checks(const ws_grid *g, const float *z_corners_dev, const void *workspace_dev,
+                             size_t workspace_bytes, const char *who) {
+    if (!grid_ok(g)) return fail(WS_EINVAL, "%s: invalid grid parameters", who);
+    if (!z_corners_dev || !workspace_dev) return fail(WS_EINVAL, "%s: NULL device pointer", who);
+    if (((uintptr_t)workspace_dev & 255) != 0) return fail(WS_EINVAL, "%s: workspace not 256-byte aligned", who);
     Layout L = layout(g);
-    if (L.nu > NRED_MAX || L.nv > NRED_MAX) return fail(WS_EINVAL, "ws_domain_init: grid too large (max %d x %d)", NRED_MAX / 2 * MX, NRED_MAX / 2 * TY);
-    if (workspace_bytes < L.total) return fail(WS_ENOMEM, "ws_domain_init: workspace %zu < %zu bytes", workspace_bytes, L.total);
-    ws_domain *d = new (std::nothrow) ws_domain();
-    if (!d) return fail(WS_ENOMEM, "ws_domain_init: host allocation failed");
+    if (L.nu > NRED_MAX || L.nv > NRED_MAX) return fail(WS_EINVAL, "%s: grid too large (max %d x %d)", who, NRED_MAX / 2 * MX, NRED_MAX / 2 * TY);
+    if (workspace_bytes < L.total) return fail(WS_ENOMEM, "%s: workspace %zu < %zu bytes", who, workspace_bytes, L.total);
+    return WS_OK;
+}
+
+// Lay the domain's fields out in the workspace, clear it, load the bathymetry
+// and the lake at rest, and check diagonal dominance.  `d` is a freshly
+// constructed handle; on failure the caller disposes of it.
+static ws_status domain_setup(ws_domain *d, const ws_grid *g, const float *z_corners_dev, void *workspace_dev,
+                              size_t workspace_bytes, void *stream, const char *who) {
+    Layout L = layout(g);
     d->g = *g;
+    d->static_dev = -1;
     d->nxp = L.nxp; d->nyp = L.nyp; d->pitch = L.pitch; d->zpitch = L.zpitch; d->nu = L.nu; d->nv = L.nv;
     d->gl = L.gl;
     d->base = (char *)workspace_dev;
@@ -457,6 +466,8 @@ extern "C" ws_status ws_domain_init(const ws_grid *g, const float *z_corners_dev
     d->fstride = L.field;
     for (int s = 0; s < 4; ++s) { d->side_type[s] = WS_BC_SOLID; d->side_width[s] = 2; d->side_expo[s] = 1.f; }
     hipStream_t st = (hipStream_t)stream;
+    // the whole layout starts at zero (a reused workspace keeps what its last
+    // domain left there)
     hipError_t e = hipMemsetAsync(d->base, 0, L.total, st);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_corners_from_z, dim3((g->nx + 1 + 255) / 256, g->ny + 1), dim3(256), 0, st,
@@ -472,17 +483,79 @@ extern "C" ws_status ws_domain_init(const ws_grid *g, const float *z_corners_dev
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e == hipSuccess && flag) e = hipMemsetAsync(d->health, 0, sizeof(int), st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) {
-        delete d;
-        return fail(WS_EHIP, "ws_domain_init: %s", hipGetErrorString(e));
-    }
-    if (flag) {
-        delete d;
-        return fail(WS_ENOTDD, "ws_domain_init: bathymetry too steep for the grid (eq. 23 not diagonally dominant)");
-    }
+    if (e != hipSuccess) return fail(WS_EHIP, "%s: %s", who, hipGetErrorString(e));
+    if (flag) return fail(WS_ENOTDD, "%s: bathymetry too steep for the grid (eq. 23 not diagonally dominant)", who);
     d->cur = 0;
     d->step = 0;
     d->t = 0.0;
+    return WS_OK;
+}
+
+extern "C" ws_status ws_domain_init(const ws_grid *g, const float *z_corners_dev, void *workspace_dev,
+                                    size_t workspace_bytes, void *stream, ws_domain **out) {
+    if (!out) return fail(WS_EINVAL, "ws_domain_init: out is NULL");
+    *out = nullptr;
+    ws_status s = init_checks(g, z_corners_dev, workspace_dev, workspace_bytes, "ws_domain_init");
+    if (s != WS_OK) return s;
+    ws_domain *d = new (std::nothrow) ws_domain();
+    if (!d) return fail(WS_ENOMEM, "ws_domain_init: host allocation failed");
+    s = domain_setup(d, g, z_corners_dev, workspace_dev, workspace_bytes, stream, "ws_domain_init");
+    if (s != WS_OK) {
+        delete d;
+        return s;
+    }
+    *out = d;
+    return WS_OK;
+}
+
+// ---- A domain in the library's own device array, for callers that cannot
+// allocate device memory.  `scratch` is one array per GPU (the code object
+// holds it on every device it is loaded on until the process ends).  In host
+// code its name is not a device address: the address is looked up once per
+// device with hipGetSymbolAddress, with that device current, and only that
+// pointer is used.  The handle lives in static storage too, so creating such
+// a domain allocates nothing, on the device or on the host.  One such domain
+// per device at a time.
+static constexpr int STATIC_MAXDEV = 64;
+static __device__ __align__(256) unsigned char scratch[WS_STATIC_WORKSPACE_BYTES];
+static void *g_scratch_ptr[STATIC_MAXDEV];     // device address of `scratch`, per device
+static bool g_scratch_held[STATIC_MAXDEV];     // a live domain uses that device's array
+alignas(ws_domain) static unsigned char g_static_dom[STATIC_MAXDEV][sizeof(ws_domain)];
+static std::mutex g_scratch_mu;
+
+extern "C" ws_status ws_domain_init_static(const ws_grid *g, const float *z_corners_dev, void *stream,
+                                           ws_domain **out) {
+    static const char *who = "ws_domain_init_static";
+    if (!out) return fail(WS_EINVAL, "%s: out is NULL", who);
+    *out = nullptr;
+    if (!grid_ok(g)) return fail(WS_EINVAL, "%s: invalid grid parameters", who);
+    const size_t need = layout(g).total;
+    if (need > WS_STATIC_WORKSPACE_BYTES)
+        return fail(WS_ENOMEM, "%s: the grid needs %zu bytes of workspace, the static array holds %zu",
+                    who, need, (size_t)WS_STATIC_WORKSPACE_BYTES);
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= STATIC_MAXDEV) return fail(WS_EINVAL, "%s: device %d out of range", who, dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_held[dev])
+        return fail(WS_EBUSY, "%s: the static workspace of device %d is held by a live domain", who, dev);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(WS_EHIP, "%s: hipGetSymbolAddress: %s", who, hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    ws_status s = init_checks(g, z_corners_dev, g_scratch_ptr[dev], WS_STATIC_WORKSPACE_BYTES, who);
+    if (s != WS_OK) return s;
+    ws_domain *d = new (g_static_dom[dev]) ws_domain();
+    s = domain_setup(d, g, z_corners_dev, g_scratch_ptr[dev], WS_STATIC_WORKSPACE_BYTES, stream, who);
+    if (s != WS_OK) {
+        d->~ws_domain();
+        return s;
+    }
+    d->static_dev = dev;
+    g_scratch_held[dev] = true;
     *out = d;
     return WS_OK;
 }
@@ -497,7 +570,15 @@ static void prof_clear(ws_domain *d) {
 
 extern "C" ws_status ws_domain_destroy(ws_domain *d) {
     if (d && d->batch) return fail(WS_EBUSY, "ws_domain_destroy: detach the domain from its batch first");
-    if (d) prof_clear(d);
+    if (!d) return WS_OK;
+    prof_clear(d);
+    if (d->static_dev >= 0) {  // a domain in the static array: release the array
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        const int dev = d->static_dev;
+        d->~ws_domain();
+        g_scratch_held[dev] = false;
+        return WS_OK;
+    }
     delete d;
     return WS_OK;
 }

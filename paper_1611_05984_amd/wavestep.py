@@ -23,6 +23,7 @@ WEST, EAST, SOUTH, NORTH = 0, 1, 2, 3
 SOLID, SPONGE, WAVES = 0, 1, 2
 EDIT_WATER, EDIT_TERRAIN = 0, 1
 READ_W, READ_H = 0, 1
+STATIC_WORKSPACE_BYTES = 80 << 20      # WS_STATIC_WORKSPACE_BYTES of the C header
 SOLVE_PCR, SOLVE_THOMAS, SOLVE_LU, SOLVE_LU2 = 0, 1, 2, 3
 K_PREDICTOR, K_CORRECTOR, K_REDUCE, K_SOLVE, K_EXPAND, K_COUNT = 0, 1, 2, 3, 4, 5
 KERNEL_NAMES = ("k_stencil[predictor]", "k_stencil[corrector]", "k_reduce", "reduced_solve", "k_expand")
@@ -71,6 +72,7 @@ def lib():
             "ws_grid_defaults": (None, [C.POINTER(Grid), i32, i32]),
             "ws_workspace_bytes": (sz, [C.POINTER(Grid)]),
             "ws_domain_init": (C.c_int, [C.POINTER(Grid), vp, vp, sz, vp, C.POINTER(vp)]),
+            "ws_domain_init_static": (C.c_int, [C.POINTER(Grid), vp, vp, C.POINTER(vp)]),
             "ws_domain_destroy": (C.c_int, [vp]),
             "ws_set_boundary": (C.c_int, [vp, i32, C.POINTER(Boundary)]),
             "ws_set_state": (C.c_int, [vp, vp, vp, vp, i32, f64, vp]),
@@ -154,7 +156,11 @@ class Domain:
     Fields are exchanged as float32 CUDA tensors of shape (ny, nx).
     """
 
-    def __init__(self, nx, ny, dx, dy, dt, z, device="cuda", stream=None, **params):
+    def __init__(self, nx, ny, dx, dy, dt, z, device="cuda", stream=None, static_workspace=False,
+                 **params):
+        """static_workspace: use the library's static device array as the
+        workspace (ws_domain_init_static: one such domain per device, grids up
+        to STATIC_WORKSPACE_BYTES) instead of a tensor allocated here."""
         import torch
         self.device = torch.device(device)
         self.g = grid(nx, ny, dx, dy, dt, **params)
@@ -162,14 +168,20 @@ class Domain:
         nbytes = workspace_bytes(self.g)
         if nbytes == 0:
             raise WaveStepError(EINVAL, "invalid grid parameters")
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         zt = torch.as_tensor(np.asarray(z) if not torch.is_tensor(z) else z,
                              dtype=torch.float32).to(self.device).contiguous()
         if zt.numel() != (ny + 1) * (nx + 1):
             raise ValueError("z must hold (ny+1)*(nx+1) corner values")
         h = C.c_void_p()
-        _check(lib().ws_domain_init(C.byref(self.g), _dptr(zt), _dptr(self.workspace), nbytes,
-                                    _stream(stream), C.byref(h)), "ws_domain_init")
+        if static_workspace:
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                _check(lib().ws_domain_init_static(C.byref(self.g), _dptr(zt), _stream(stream),
+                                                   C.byref(h)), "ws_domain_init_static")
+        else:
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            _check(lib().ws_domain_init(C.byref(self.g), _dptr(zt), _dptr(self.workspace), nbytes,
+                                        _stream(stream), C.byref(h)), "ws_domain_init")
         self._h = h
 
     def close(self):

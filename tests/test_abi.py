@@ -57,3 +57,25 @@ def test_init_rejects_bad_arguments_without_touching_the_device():
                             C.byref(h)) == ws.EINVAL
     assert L.ws_advance(None, 1, None) == ws.EINVAL
     assert L.ws_query(None, None, None, None, None) == ws.EINVAL
+
+
+def test_static_init_refuses_before_touching_the_device():
+    """ws_domain_init_static checks the grid against its static array before
+    any device call: an invalid grid is WS_EINVAL, a grid whose workspace
+    exceeds WS_STATIC_WORKSPACE_BYTES is WS_ENOMEM with both sizes named."""
+    txt = open(os.path.join(ROOT, "include", "wavestep.h")).read()
+    m = re.search(r"#define WS_STATIC_WORKSPACE_BYTES \(\(size_t\)(\d+) << (\d+)\)", txt)
+    assert m and int(m.group(1)) << int(m.group(2)) == ws.STATIC_WORKSPACE_BYTES
+    L = ws.lib()
+    h = C.c_void_p()
+    fits = ws.grid(1024, 512, 0.05, 0.05, 0.004)
+    assert ws.workspace_bytes(fits) <= ws.STATIC_WORKSPACE_BYTES
+    big = ws.grid(1024, 1024, 0.05, 0.05, 0.004)
+    need = ws.workspace_bytes(big)
+    assert need > ws.STATIC_WORKSPACE_BYTES
+    assert L.ws_domain_init_static(C.byref(big), C.c_void_p(256), None, C.byref(h)) == ws.ENOMEM
+    msg = L.ws_last_error().decode()
+    assert str(need) in msg and str(ws.STATIC_WORKSPACE_BYTES) in msg and not h.value
+    bad = ws.grid(1, 64, 0.1, 0.1, 0.01)
+    assert L.ws_domain_init_static(C.byref(bad), C.c_void_p(256), None, C.byref(h)) == ws.EINVAL
+    assert L.ws_domain_init_static(C.byref(fits), C.c_void_p(256), None, None) == ws.EINVAL
