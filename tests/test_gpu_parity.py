@@ -384,6 +384,43 @@ def test_terrain_edit_keeps_velocity_like_oracle():
     check(gpu, ora, 0.3, h0, rel=1e-4, what="20 steps after the edit")
 
 
+def test_restore_after_time_step_change_restarts_history():
+    """A snapshot restored after ws_update_grid changed dt brings back the
+    state, bathymetry and time but restarts the multistep history (step 0,
+    two Euler steps at the new dt): the run then matches the oracle
+    hot-started from the same state at the new dt."""
+    ws = _ws()
+    w = wl.config2(nx=160, ny=72, seed=9)
+    say("case: restore after a time-step change, %s" % w.name)
+    gpu, ora = build_pair(w)
+    gpu.advance(20)
+    ora.advance(20)
+    snap = gpu.snapshot()
+    s20 = ora.state()
+    t20 = ora.t
+    gpu.advance(10)
+    dt2 = 0.5 * w.dt
+    gpu.update(dt=dt2)
+    gpu.restore(snap)
+    step, t, health = gpu.query()
+    assert step == 0 and t == t20 and health == 0
+    z = w.z.astype(np.float32).astype(np.float64)
+    ora2 = o.Domain(w.nx, w.ny, w.dx, w.dy, dt2, z)
+    for s, side in enumerate(w.sides):
+        if side.kind != wl.SOLID:
+            ora2.set_boundary(s, side.kind, side.width, side.amp, side.period, side.theta,
+                              side.phase or None)
+    ora2.set_state(*s20, t=t20)
+    for n in (2, 28):
+        gpu.advance(n)
+        ora2.advance(n)
+        check(gpu, ora2, 0.03, 0.5, rel=1e-4, what="after restore, step %d at dt/2" % ora2.step)
+    # a snapshot restored at its own time step keeps the history
+    gpu.update(dt=w.dt)
+    gpu.restore(snap)
+    assert gpu.query()[0] == 20
+
+
 def test_steep_terrain_edit_rejected_unchanged():
     say("case: rejected terrain edit")
     ws = _ws()
@@ -396,25 +433,65 @@ def test_steep_terrain_edit_rejected_unchanged():
 
 
 # -------------------------------------------------------------- full sizes
-def test_config2_full_size_parity():
-    """Config 2 at its full 1024 x 512 size, 40 steps (beach, bumps, sine maker)."""
-    say("case: config2 1024x512, 40 steps")
-    w = wl.config2(steps=40)
+def test_config2_full_size_500_steps():
+    """Config 2 at its full 1024 x 512 size for 500 steps (beach with a moving
+    shoreline, seeded bumps, west sine maker a = 0.03 m, T = 2 s): eta within
+    1e-4 a over the cells wet in both runs, P and Q within 1e-4 a sqrt(g d);
+    the shoreline (cells wet in one run only) reported."""
+    say("case: config2 1024x512, 500 steps")
+    w = wl.config2(steps=500)
     gpu, ora = build_pair(w)
-    gpu.advance(40)
-    ora.advance(40)
-    check(gpu, ora, 0.03, 0.5, rel=1e-4, what="config2 step 40")
+    a, d = 0.03, 0.5
+    for n in (3, 497):
+        gpu.advance(n)
+        ora.advance(n)
+    ge, gP, gQ = gpu.state_numpy()
+    oe, oP, oQ = ora.state()
+    b, _ = ora.bathy()
+    wet = ((oe - b) > 1e-4) & ((ge - b) > 1e-4)
+    shore = ((oe - b) > 1e-4) != ((ge - b) > 1e-4)
+    de = np.abs(ge - oe)[wet].max()
+    dP, dQ = np.abs(gP - oP).max(), np.abs(gQ - oQ).max()
+    say("  step 500: wet cells %d, max|d eta| wet = %.3e (1e-4 a = %.1e), max|dP| = %.3e, "
+        "max|dQ| = %.3e; cells wet in one run only: %d" % (wet.sum(), de, 1e-4 * a, dP, dQ, shore.sum()))
+    assert de <= 1e-4 * a
+    c = math.sqrt(G * d)
+    assert dP <= 1e-4 * a * c and dQ <= 1e-4 * a * c
+    assert np.all(ge >= b.astype(np.float32) - 1e-6)          # w >= B everywhere
+    step, t, health = gpu.query()
+    assert health == 0 and step == ora.step == 500
 
 
-def test_config3_full_size_parity_and_rest():
-    """Config 3 at 4096 x 4096 (the benchmark's launch shapes): 3 steps (two
-    Euler steps, then AB3 + 2 AM4) against the oracle, JONSWAP maker, sponge."""
-    say("case: config3 4096x4096, 3 steps")
+def _cached_tuning(nx, ny, n_corr=2, model=0):
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_1611_05984_amd", "tuning_cache.txt")
+    for line in open(path):
+        f = [int(v) for v in line.split()]
+        if f[:4] == [nx, ny, n_corr, model]:
+            return path, tuple(f[4:8])
+    raise AssertionError("no cached tuning for %dx%d" % (nx, ny))
+
+
+def test_config3_benchmark_shapes_100_steps():
+    """Config 3 at 4096 x 4096 in the launch configuration the benchmark times:
+    the tuning is read from the autotuner's cache exactly as bench.py does
+    (8-row stencil strips, the factored reduced solve in workgroup form), then
+    100 steps (two Euler steps, 98 AB3 + 2 AM4 steps) against the oracle,
+    with the 64-component JONSWAP maker and the east sponge.  a0 = Hs/2."""
+    say("case: config3 4096x4096, benchmark launch shapes, 100 steps")
+    ws = _ws()
     w = wl.config3()
     gpu, ora = build_pair(w)
-    gpu.advance(3)
-    ora.advance(3)
-    check(gpu, ora, 1.0, 30.0, rel=1e-5, what="config3 step 3")
+    path, want = _cached_tuning(w.nx, w.ny)
+    got = gpu.tune(cache_path=path)
+    say("  tuning from the cache: %s" % (got,))
+    assert tuple(got) == want and want[2] == ws.SOLVE_LU
+    a0, depth = 0.5, 30.0
+    for n in (3, 97):
+        gpu.advance(n)
+        ora.advance(n)
+        check(gpu, ora, a0, depth, rel=(2e-5 if ora.step == 3 else 1e-4), what="config3 step %d" % ora.step)
 
 
 def test_maximum_grid_transposition_symmetry():
