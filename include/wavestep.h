@@ -178,6 +178,14 @@ ws_status ws_update_grid(ws_domain *d, const ws_grid *g, void *stream);
 ws_status ws_set_state(ws_domain *d, const float *w, const float *P, const float *Q,
                        int32_t pitch, double t, void *stream);
 
+/* Gauges (sec. 3.2: the solver can save w, P, Q at chosen grid points only).
+ * ij_dev: device array of n cell index pairs (i, j); out_dev: device array of
+ * 4n floats receiving (w, h = w - cell bottom, P, Q) of each gauge's cell in
+ * the current state; a pair outside the grid gives four NaNs.  Asynchronous
+ * and allocation-free, so a caller can record a time series by pointing
+ * out_dev at successive rows of its own buffer between steps. */
+ws_status ws_read_gauges(ws_domain *d, int32_t n, const int32_t *ij_dev, float *out_dev, void *stream);
+
 /* Superpose a solitary wave of height H (sign allowed), direction theta
  * (radians), crest through (x0, y0), eqs. 33-36, where the still water depth
  * is positive.  The depth of eqs. 35-36 is the still water depth of the
@@ -215,7 +223,12 @@ ws_status ws_apply_edit(ws_domain *d, int32_t kind, double x0, double y0, double
  * header synchronously, returns WS_EINVAL if the snapshot was taken from a
  * domain of another grid size, corrector count or model, then copies
  * asynchronously.  Stepping on after a restore continues the run exactly as
- * it would have continued from the snapshot. */
+ * it would have continued from the snapshot.  A snapshot taken while the
+ * domain ran at another time step (ws_update_grid changed dt since) restores
+ * its state, bathymetry and time but restarts the multistep history: the
+ * step count becomes 0 and the next two steps are Euler steps, since history
+ * levels spaced by the old dt do not fit the multistep formulas at the new
+ * one. */
 size_t ws_snapshot_bytes(const ws_domain *d);
 /* The same for a grid not yet created (0 if the grid is invalid): what a
  * caller budgeting device memory for a domain and its checkpoint needs. */

@@ -243,6 +243,27 @@ __global__ void k_read(Dom d, const float *e, const float *p, const float *q, in
     if (Q) Q[s] = q[o];
 }
 
+// Gauges: the state at chosen cells.  Gauge k at cell (ij[2k], ij[2k+1])
+// gives out[4k..4k+3] = (w, h, P, Q); a cell outside the grid gives NaNs.
+__global__ void k_gauges(Dom d, const float *e, const float *p, const float *q, float ws, const int *ij, int n,
+                         float *out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int i = ij[2 * k], j = ij[2 * k + 1];
+    float v0 = NAN, v1 = NAN, v2 = NAN, v3 = NAN;
+    if (i >= 0 && i < d.nx && j >= 0 && j < d.ny) {
+        const size_t o = (size_t)j * d.pitch + i;
+        v0 = e[o] + ws;
+        v1 = e[o] + cell_Dc(d, i, j);
+        v2 = p[o];
+        v3 = q[o];
+    }
+    out[4 * k] = v0;
+    out[4 * k + 1] = v1;
+    out[4 * k + 2] = v2;
+    out[4 * k + 3] = v3;
+}
+
 // Surface kept at or above the bottom, discharges desingularized where thin.
 __device__ __forceinline__ void shore_fix(const Dom &d, int i, int j, float *e, float *p, float *q) {
     size_t o = (size_t)j * d.pitch + i;
@@ -732,11 +753,12 @@ struct SnapHeader {
     unsigned long long magic;
     int nx, ny, pitch, zpitch;
     long long step;
-    double t;
+    double t, dt;
     int n_corr, model;
     unsigned long long field_bytes, corner_bytes, total;
 };
-static const unsigned long long SNAP_MAGIC = 0x3130504e53535757ull;  // "WWSSNP01"
+static_assert(sizeof(SnapHeader) <= 256, "the snapshot header fills the first 256 bytes");
+static const unsigned long long SNAP_MAGIC = 0x3230504e53535757ull;  // "WWSSNP02"
 
 extern "C" size_t ws_snapshot_bytes_grid(const ws_grid *g) {
     if (!grid_ok(g)) return 0;
@@ -767,7 +789,7 @@ extern "C" ws_status ws_snapshot(ws_domain *d, void *dst_dev, size_t bytes, void
     std::memset(&h, 0, sizeof h);
     h.magic = SNAP_MAGIC;
     h.nx = d->g.nx; h.ny = d->g.ny; h.pitch = d->pitch; h.zpitch = d->zpitch;
-    h.step = d->step; h.t = d->t;
+    h.step = d->step; h.t = d->t; h.dt = d->g.dt;
     h.n_corr = d->g.n_corr; h.model = d->g.model;
     h.field_bytes = fb; h.corner_bytes = cb; h.total = need;
     char *p = (char *)dst_dev;
@@ -800,7 +822,9 @@ extern "C" ws_status ws_restore(ws_domain *d, const void *src_dev, size_t bytes,
     HIPCHK(hipMemcpyAsync(d->D, p, cb, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemsetAsync(d->health, 0, sizeof(int), st));
     d->cur = 0;
-    d->step = h.step;
+    // history levels taken at another time step are not spaced by this one:
+    // the multistep history restarts (two Euler steps), as after a change of dt
+    d->step = h.dt == d->g.dt ? h.step : 0;
     d->t = h.t;
     d->lu_valid = false;  // bathymetry restored
     batch_touch(d);
@@ -829,6 +853,18 @@ extern "C" ws_status ws_read(ws_domain *d, int32_t what, float *first, float *P,
     hipLaunchKernelGGL(k_read, cells_grid(d->g.nx, d->g.ny), dim3(256), 0, (hipStream_t)stream, m,
                        d->st[d->cur][0], d->st[d->cur][1], d->st[d->cur][2], what, (float)d->g.still_water,
                        first, P, Q, pitch);
+    HIPCHK(hipGetLastError());
+    return WS_OK;
+}
+
+extern "C" ws_status ws_read_gauges(ws_domain *d, int32_t n, const int32_t *ij_dev, float *out_dev,
+                                    void *stream) {
+    if (!d || n < 0 || (n > 0 && (!ij_dev || !out_dev))) return fail(WS_EINVAL, "ws_read_gauges: bad argument");
+    if (busy_check(d, "ws_read_gauges") != WS_OK) return WS_EBUSY;
+    if (n == 0) return WS_OK;
+    Dom m = make_dom(d);
+    hipLaunchKernelGGL(k_gauges, dim3((n + 63) / 64), dim3(64), 0, (hipStream_t)stream, m, d->st[d->cur][0],
+                       d->st[d->cur][1], d->st[d->cur][2], (float)d->g.still_water, ij_dev, n, out_dev);
     HIPCHK(hipGetLastError());
     return WS_OK;
 }

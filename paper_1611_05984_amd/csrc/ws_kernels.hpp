@@ -1209,7 +1209,9 @@ __device__ __forceinline__ void expand_body(const SolveArgs &A, SolveTile &s, in
         A.pout[o] = P;
         A.qout[o] = Q;
     }
-    if (bad) atomicOr(A.health, 1);
+    // one atomic per wave: a non-finite state must not serialize every thread
+    // of the launch on the health word
+    if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(A.health, 1);
 }
 
 __global__ __launch_bounds__(NT) void k_expand(SolveArgs A) {

@@ -79,6 +79,7 @@ def lib():
             "ws_add_solitary": (C.c_int, [vp, f64, f64, f64, f64, vp]),
             "ws_advance": (C.c_int, [vp, i64, vp]),
             "ws_read": (C.c_int, [vp, i32, vp, vp, vp, i32, vp]),
+            "ws_read_gauges": (C.c_int, [vp, i32, vp, vp, vp]),
             "ws_apply_edit": (C.c_int, [vp, i32, f64, f64, f64, f64, vp]),
             "ws_query": (C.c_int, [vp, vp, C.POINTER(i64), C.POINTER(f64), C.POINTER(i32)]),
             "ws_last_error": (C.c_char_p, []),
@@ -232,6 +233,20 @@ class Domain:
         out = self.read(what)
         torch.cuda.current_stream().synchronize()
         return tuple(a.cpu().numpy() for a in out)
+
+    def gauges(self, ij, out=None, stream=None):
+        """State at gauge cells: ij is an int32 CUDA tensor of shape (n, 2)
+        holding (i, j) pairs; writes (w, h, P, Q) per gauge into `out` (a
+        float32 CUDA tensor of n * 4 elements, e.g. a row of a time-series
+        buffer; allocated when None) without synchronizing, and returns it."""
+        import torch
+        assert ij.dtype == torch.int32 and ij.is_cuda and ij.is_contiguous() and ij.shape[-1] == 2
+        n = ij.numel() // 2
+        if out is None:
+            out = torch.empty((n, 4), dtype=torch.float32, device=self.device)
+        assert out.dtype == torch.float32 and out.is_contiguous() and out.numel() == 4 * n
+        _check(lib().ws_read_gauges(self._h, n, _dptr(ij), _dptr(out), _stream(stream)), "ws_read_gauges")
+        return out
 
     def apply_edit(self, kind, x0, y0, amp, sigma, stream=None):
         """Returns the status (0, or ENOTDD for a rejected terrain edit)."""
