@@ -4,12 +4,19 @@ components at the west side, 64-cell sponge east, walls north/south,
 fractal bathymetry noise; predictor + 2 correctors per step).
 
 Prints one JSON line.  `value` = cells * steps / wall seconds of the timed
-steps (inputs resident in HBM).  `roofline` reports the dominant kernel:
-algorithmic bytes per launch (the kernel's compulsory reads and writes, see
-ALG_BYTES) divided by its average duration, timed with HIP events recorded on
-the library's launch stream over a second pass of the same steps.
-`cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
-workload (after its two Euler start-up steps, a few full steps).
+steps (inputs resident in HBM), the median over `--windows` timed windows of
+`--steps` steps each.  `roofline` reports the kernel with the largest share
+of the step time: its algorithmic bytes per launch (the kernel's compulsory
+reads and writes, see alg_words) divided by its average duration, timed with
+HIP events recorded on the library's launch stream over a further window;
+beside it, the whole step on the fused-ideal byte count (88 B per cell for
+the predictor pass and 84 B per corrector pass: 256 B at K = 2) and on this
+design's own count.  `copy_GBs` is the rate of a hand-written streaming
+kernel with the corrector stencil's access shape (7 fields read, 3 written,
+one wave per 64-column strip), measured in every run.  `cpu_baseline` times
+the FP64 CPU oracle on a bounded sample of the same workload on all host
+threads (`--cpu-table` adds 1-thread and all-thread rates of the three
+single-domain workloads).
 """
 import argparse
 import json
@@ -21,6 +28,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# fused-ideal compulsory bytes per cell of one pass: predictor 22 words, corrector 21
+SURVEY_PRED_B, SURVEY_CORR_B = 88.0, 84.0
+# non-packed FP32 VALU issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (lane-instructions/s);
+# packed FP32 instructions are disabled in this build
+VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
 TUNING_CACHE = os.path.join(ROOT, "paper_1611_05984_amd", "tuning_cache.txt")
 
 # Compulsory FP32 words per cell of each kernel class (reads + writes), for
@@ -47,21 +59,18 @@ def alg_words(solver):
             "k_reduce": reduce_w, "reduced_solve": solve_w, "k_expand": 8.25}
 
 
-# kernel function -> its launch classes
-FUNCS = {"k_stencil": ("k_stencil[predictor]", "k_stencil[corrector]"), "k_reduce": ("k_reduce",),
-         "reduced_solve": ("reduced_solve",), "k_expand": ("k_expand",)}
-
-
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--windows", type=int, default=5, help="timed windows of --steps steps (median)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=4096, help="grid side (cells)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=12)
-    ap.add_argument("--copy-calib", action="store_true",
-                    help="also run a 256 MiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--cpu-table", action="store_true",
+                    help="also time the oracle on 1 and all threads on the 128x64 basin (500 steps), "
+                         "the 1024x512 beach (200) and the 4096^2 shelf (3)")
     ap.add_argument("--retune", action="store_true",
                     help="measure the launch shapes instead of reading the tuning cache")
     ap.add_argument("--no-batched", action="store_true",
@@ -77,24 +86,96 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(w, steps):
+def cpu_model():
+    """Host CPU model name and the logical CPUs this process may use."""
+    name = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return name, len(os.sched_getaffinity(0))
+
+
+def _oracle_rate(w, steps, threads):
+    """Cell-updates/s of the oracle on workload w: `steps` full steps after
+    its two Euler start-up steps (untimed), on `threads` OpenMP threads."""
     import numpy as np
     import oracle
+    used = oracle.set_threads(threads)
     z = w.z.astype(np.float32).astype(np.float64)
     D = oracle.Domain(w.nx, w.ny, w.dx, w.dy, w.dt, z)
     for s, side in enumerate(w.sides):
         if side.kind != 0:
             D.set_boundary(s, side.kind, side.width, side.amp, side.period, side.theta,
                            side.phase or None)
-    D.advance(2)                      # Euler start-up steps (one pass each), untimed
+    for (H, th, x0, y0) in w.solitary:
+        D.add_solitary(H, th, x0, y0)
+    D.advance(2)
     t = time.perf_counter()
     D.advance(steps)
     dt = time.perf_counter() - t
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": w.nx * w.ny * steps / dt, "unit": "cell-updates/s", "cores": threads,
-            "kind": "oracle",
+    return w.nx * w.ny * steps / dt, dt, used
+
+
+def cpu_baseline(w, steps):
+    import oracle
+    all_threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
+    rate, dt, used = _oracle_rate(w, steps, all_threads)
+    model, ncpu = cpu_model()
+    return {"value": rate, "unit": "cell-updates/s", "cores": used, "kind": "oracle",
+            "cpu_model": model, "cpus_available": ncpu,
             "sample": "%s, %d full steps (predictor + 2 correctors) after the 2 Euler "
-                      "start-up steps, FP64, %.1f s" % (w.name, steps, dt)}
+                      "start-up steps, FP64, %d threads, %.1f s" % (w.name, steps, used, dt)}
+
+
+def cpu_table(wl):
+    """The oracle on 1 thread and on all threads: 128x64 basin 500 steps,
+    1024x512 beach 200 steps, 4096^2 shelf 3 steps (after the start-up)."""
+    all_threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
+    rows = []
+    for w, steps in ((wl.config1(), 500), (wl.config2(steps=200), 200), (wl.config3(), 3)):
+        for th in (1, all_threads):
+            rate, dt, used = _oracle_rate(w, steps, th)
+            rows.append({"workload": w.name, "steps": steps, "threads": used,
+                         "cell_updates_per_s": rate, "s_per_step": dt / steps})
+            print("bench: oracle %s %d steps, %d threads: %.3g cell-updates/s"
+                  % (w.name, steps, used, rate), file=sys.stderr, flush=True)
+    return rows
+
+
+def stream_ceilings(torch, n):
+    """HBM rates (GB/s, bytes moved / event time) of the hand-written
+    streaming kernels: a 16-byte-lane copy of one n x n field, and the
+    corrector (7 read + 3 written fields) and predictor (12 + 11) shapes of
+    the stencil at 8 rows per wave."""
+    import ctypes as C
+    from paper_1611_05984_amd import build as bld
+    if not os.path.exists(bld.PROBE_LIB):
+        raise RuntimeError("libwsprobe.so is not built; run paper_1611_05984_amd/build.py")
+    L = C.CDLL(bld.PROBE_LIB)
+    L.wsp_stream.restype = C.c_int
+    L.wsp_stream.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int,
+                             C.c_void_p, C.POINTER(C.c_float)]
+    pitch = (n + 63) // 64 * 64
+    out = {}
+    st = torch.cuda.current_stream()
+    for kind, nr, nw, key in ((0, 1, 1, "copy16_GBs"), (1, 7, 3, "stencil_7r3w_GBs"),
+                              (2, 12, 11, "stencil_12r11w_GBs")):
+        a = torch.ones(nr * n * pitch, dtype=torch.float32, device="cuda")
+        b = torch.empty(nw * n * pitch, dtype=torch.float32, device="cuda")
+        ms = C.c_float(0.0)
+        rc = L.wsp_stream(kind, C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), pitch, n, 8, 20,
+                          C.c_void_p(st.cuda_stream), C.byref(ms))
+        if rc != 0:
+            raise RuntimeError("wsp_stream kind %d failed (%d)" % (kind, rc))
+        out[key] = (nr + nw) * n * pitch * 4 / (ms.value / 1e3) / 1e9
+        del a, b
+    torch.cuda.empty_cache()
+    out["shape"] = "%dx%d floats per field" % (n, pitch)
+    return out
 
 
 def _make(ws, w, **params):
@@ -180,15 +261,29 @@ def serving(args):
 
 def k_variants(args, torch, ws, wl):
     """Rates of the big-domain workload with K = 0 and K = 1 correctors, and
-    in the NLSW model (K = 2; no dispersion, so no tridiagonal solves)."""
+    in the NLSW model (K = 2; no dispersion, so no tridiagonal solves), each
+    with its own launch shapes from the autotuner (read from its cache when
+    that shape was measured before).  The AB3 predictor alone (K = 0) is
+    unstable on this dispersive workload (the state turns non-finite after
+    60-70 steps, in the FP64 oracle too), so it is timed over three windows of
+    10 steps right after the start-up, while the state is finite; every rate
+    is reported with the health word at the end of its windows (a rate of a
+    non-finite state is reported as null)."""
     w = wl.config3(n=args.n)
     out = {}
-    for key, params in (("K0", dict(n_corr=0)), ("K1", dict(n_corr=1)), ("nlsw_K2", dict(model=ws.NLSW))):
+    for key, params, n in (("K0", dict(n_corr=0), 10), ("K1", dict(n_corr=1), max(10, args.steps // 2)),
+                           ("nlsw_K2", dict(model=ws.NLSW), max(10, args.steps // 2))):
         d = _make(ws, w, **params)
         d.advance(5)
-        n = max(10, args.steps // 4)
-        t = _timed(torch, lambda k: d.advance(k), n)
-        out[key] = w.nx * w.ny * n / t
+        tun = d.tune(cache_path=None if args.retune else TUNING_CACHE)
+        d.advance(3)
+        rates = [w.nx * w.ny * n / _timed(torch, lambda k: d.advance(k), n) for _ in range(3)]
+        step, _, health = d.query()
+        out[key] = sorted(rates)[1] if health == 0 else None
+        out[key + "_tuning"] = list(tun)
+        out[key + "_healthy_at_step"] = [step, health == 0]
+        print("bench: %s tuned %s: %s cell-updates/s (health %d at step %d)"
+              % (key, tun, out[key], health, step), file=sys.stderr, flush=True)
         d.close()
         del d
         torch.cuda.empty_cache()
@@ -208,21 +303,8 @@ def main():
     from paper_1611_05984_amd import workloads as wl
 
     torch.cuda.set_device(0)
-    copy_gbs = None
-    if args.copy_calib:
-        # 256 MiB device-to-device copy: calibrates the HBM byte counters of a
-        # profiled run and gives the practical copy bandwidth of this GPU
-        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        for _ in range(5):
-            dst.copy_(src)
-        ev1.record()
-        torch.cuda.synchronize()
-        copy_gbs = 5 * 2 * src.numel() * 4 / (ev0.elapsed_time(ev1) / 1e3) / 1e9
-        del src, dst
+    ceil = stream_ceilings(torch, args.n)
+    print("bench: streaming ceilings %s" % json.dumps(ceil), file=sys.stderr, flush=True)
     w = wl.config3(n=args.n)
     D = ws.Domain(w.nx, w.ny, w.dx, w.dy, w.dt, w.z, device="cuda:0")
     for s, side in enumerate(w.sides):
@@ -238,47 +320,56 @@ def main():
     D.advance(2)
     torch.cuda.synchronize()
 
-    t0 = time.perf_counter()
-    D.advance(args.steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    cells = w.nx * w.ny
+    walls = []
+    for _ in range(max(1, args.windows)):
+        t0 = time.perf_counter()
+        D.advance(args.steps)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
     step, tsim, health = D.query()
     if health:
         print("bench: non-finite state", file=sys.stderr)
         sys.exit(1)
-    cells = w.nx * w.ny
+    wall = sorted(walls)[len(walls) // 2]
     value = cells * args.steps / wall
-    print("bench: timed %d steps in %.3f s" % (args.steps, wall), file=sys.stderr, flush=True)
+    print("bench: %d windows of %d steps: %s s" % (len(walls), args.steps, ["%.4f" % x for x in walls]),
+          file=sys.stderr, flush=True)
 
-    # per-kernel durations from HIP events on the launch stream (second pass)
+    # per-kernel durations from HIP events on the launch stream (another window)
     D.profile(True)
     D.advance(args.steps)
     prof = D.profile_collect()
     D.profile(False)
     tot = sum(ms for ms, n in prof.values())
     ALG_WORDS = alg_words(tuning[2])
-    fsum = {f: (sum(prof[c][0] for c in cs), sum(prof[c][1] for c in cs),
-                sum(ALG_WORDS[c] * prof[c][1] for c in cs)) for f, cs in FUNCS.items()}
-    dom_func = max(fsum, key=lambda f: fsum[f][0])
-    # kernel symbol as the profiler names it (template instance of the tuned shape)
-    dom_name = {"k_stencil": "k_stencil_p<%d>,k_stencil_c<%d>" % (tuning[0], tuning[3] or tuning[0]),
-                "reduced_solve": ("k_pcr", "k_thomas", "k_luw_solve", "k_lu2_solve")[tuning[2]]}.get(dom_func, dom_func)
-    dom_ms, dom_n, dom_words = fsum[dom_func]
-    avg_s = dom_ms / dom_n / 1e3
-    alg_bytes = dom_words / dom_n * 4.0 * cells
-    achieved = alg_bytes / avg_s / 1e9
-    step_words = (ALG_WORDS["k_stencil[predictor]"] + 2 * ALG_WORDS["k_stencil[corrector]"] +
-                  3 * (ALG_WORDS["k_reduce"] + ALG_WORDS["reduced_solve"] + ALG_WORDS["k_expand"]))
-    kernels = {k: {"ms_avg": (ms / n if n else 0.0), "launches": n,
-                   "share": (ms / tot if tot else 0.0),
+    kernels = {k: {"symbol": kernel_symbol(k, tuning), "ms_avg": (ms / n if n else 0.0), "launches": n,
+                   "share": (ms / tot if tot else 0.0), "alg_bytes_per_cell": ALG_WORDS[k] * 4,
                    "alg_GBs": (ALG_WORDS[k] * 4 * cells / (ms / n / 1e3) / 1e9 if n else 0.0)}
                for k, (ms, n) in prof.items()}
-    traffic = None
+    # the dominant kernel: the largest share of the step's kernel time
+    dom = max((k for k in kernels if kernels[k]["launches"]), key=lambda k: kernels[k]["share"])
+    dom_name = kernels[dom]["symbol"]
+    avg_s = kernels[dom]["ms_avg"] / 1e3
+    alg_bytes = ALG_WORDS[dom] * 4.0 * cells
+    achieved = alg_bytes / avg_s / 1e9
+    kernel_ms_step = tot / args.steps
+    step_words = (ALG_WORDS["k_stencil[predictor]"] + 2 * ALG_WORDS["k_stencil[corrector]"] +
+                  3 * (ALG_WORDS["k_reduce"] + ALG_WORDS["reduced_solve"] + ALG_WORDS["k_expand"]))
+    survey_b = SURVEY_PRED_B + 2 * SURVEY_CORR_B
+    # counter figures of the dominant kernel from the committed profile, used
+    # only while the kernel sources are those the counters were taken on
+    traffic, valu = None, None
     tpath = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tpath):
         tr = json.load(open(tpath))
         if tr.get("kernel") == dom_name and tr.get("source_hash") == _source_hash():
             traffic = tr.get("bytes_per_launch")
+            if tr.get("valu_lane_instr_per_launch"):
+                li = tr["valu_lane_instr_per_launch"]
+                valu = {"lane_instr_per_cell": li / cells,
+                        "issue_frac": li / (kernels[dom]["ms_avg"] / 1e3) / VALU_ISSUE_PEAK,
+                        "peak_lane_instr_per_s": VALU_ISSUE_PEAK}
 
     out = {
         "metric": "cell-updates/s per full step (FP32)",
@@ -299,14 +390,20 @@ def main():
                               "pcr_threads": tuning[1],
                               "solver": ("pcr", "thomas", "lu", "lu2")[tuning[2]]},
                    "boundaries": "W waves(64 comps) / E sponge(64) / N,S walls"},
+        "windows_s": walls,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": dom_name, "kernel_ms_avg": dom_ms / dom_n,
-                     "alg_bytes_per_launch": alg_bytes},
-        "copy_GBs": copy_gbs,
-        "step_hbm": {"alg_bytes_per_cell_step": step_words * 4,
-                     "alg_GBs": value * step_words * 4 / 1e9,
-                     "frac_of_peak": value * step_words * 4 / 1e9 / HBM_PEAK_GBS},
+                     "kernel": dom_name, "kernel_ms_avg": kernels[dom]["ms_avg"], "valu": valu,
+                     "alg_bytes_per_launch": alg_bytes, "alg_bytes_per_cell": ALG_WORDS[dom] * 4,
+                     "step": {"alg_bytes_per_cell_fused_ideal": survey_b,
+                              "achieved_GBs": value * survey_b / 1e9,
+                              "frac": value * survey_b / 1e9 / HBM_PEAK_GBS,
+                              "alg_bytes_per_cell_this_design": step_words * 4,
+                              "achieved_GBs_this_design": value * step_words * 4 / 1e9,
+                              "frac_this_design": value * step_words * 4 / 1e9 / HBM_PEAK_GBS,
+                              "kernel_ms_per_step": kernel_ms_step}},
+        "copy_GBs": ceil["stencil_7r3w_GBs"],
+        "copy_ceilings": ceil,
         "kernels": kernels,
         "sim": {"step": step, "t_s": tsim},
     }
@@ -325,6 +422,8 @@ def main():
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+        if args.cpu_table:
+            out["cpu_baseline"]["table"] = cpu_table(wl)
     print(json.dumps(out), flush=True)
 
 

@@ -35,9 +35,14 @@ def lib():
     """Load (building on first use if absent) the oracle shared library."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
+        path = _build.LIB
+        if os.environ.get("WAVESTEP_ORACLE_SANITIZE") == "1":
+            path = _build.SAN_LIB
+            if not os.path.exists(path):
+                _build.build(sanitize=True)
+        elif not os.path.exists(path):
             _build.build()
-        L = C.CDLL(_build.LIB)
+        L = C.CDLL(path)
         L.or_create.restype = C.c_void_p
         L.or_create.argtypes = [C.POINTER(Params), _dp]
         L.or_destroy.argtypes = [C.c_void_p]
@@ -61,6 +66,8 @@ def lib():
         L.or_get_time.argtypes = [C.c_void_p]
         L.or_diag_dominant.argtypes = [C.c_void_p]
         L.or_eval_rhs.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_double] + [_dp] * 7
+        L.or_set_threads.restype = C.c_int
+        L.or_set_threads.argtypes = [C.c_int]
         L.or_set_clock.argtypes = [C.c_void_p, C.c_int64, C.c_double]
         L.or_set_history.argtypes = [C.c_void_p, C.c_int] + [_dp] * 5
         L.or_eval_solve.argtypes = [C.c_void_p, _dp, _dp, C.c_double, _dp, _dp]
@@ -224,6 +231,12 @@ class Domain:
         P, Q = np.empty((self.ny, self.nx)), np.empty((self.ny, self.nx))
         lib().or_eval_solve(self._h, _f64(U, n), _f64(V, n), float(t), P, Q)
         return P, Q
+
+
+def set_threads(n=0):
+    """OpenMP threads of the oracle's loops (n <= 0: unchanged); returns the
+    number in use."""
+    return int(lib().or_set_threads(int(n)))
 
 
 def thomas(a, b, c, r):

@@ -30,6 +30,7 @@
  * the same stated reading.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -1103,6 +1104,14 @@ int or_eval_rhs(or_domain *D, const double *w, const double *P, const double *Q,
     free(Ub);
     free(Vb);
     return 0;
+}
+
+/* Threads of the OpenMP row/column loops for the following calls (n <= 0:
+ * leave unchanged); returns the number now in use.  Results do not depend
+ * on it. */
+int or_set_threads(int n) {
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
 }
 
 /* Set the number of completed steps and the time.  Together with

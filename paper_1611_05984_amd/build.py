@@ -1,7 +1,8 @@
-"""Build libwavestep.so (the gfx950 time step) in-tree with hipcc.
+"""Build libwavestep.so (the gfx950 time step) and libwsprobe.so (HBM
+streaming ceilings the benchmark measures beside it) in-tree with hipcc.
 
-Packed FP32 instructions are disabled (-packed-fp32-ops); the library is
-position independent and links only the HIP runtime.
+Packed FP32 instructions are disabled (-packed-fp32-ops); the libraries are
+position independent and link only the HIP runtime.
 """
 import os
 import subprocess
@@ -9,8 +10,9 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc", "wavestep.hip")
-DEPS = [os.path.join(HERE, "csrc", f) for f in ("ws_device.hpp", "ws_kernels.hpp")]
 LIB = os.path.join(HERE, "libwavestep.so")
+PROBE_SRC = os.path.join(HERE, "csrc", "ws_probe.hip")
+PROBE_LIB = os.path.join(HERE, "libwsprobe.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -18,16 +20,21 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Wall", "-Wno-unused-result"]
 
 
-def build(verbose: bool = False) -> str:
-    cmd = [HIPCC] + FLAGS + ["-o", LIB + ".tmp", SRC]
+def _hipcc(src: str, lib: str, verbose: bool) -> str:
+    cmd = [HIPCC] + FLAGS + ["-o", lib + ".tmp", src]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libwavestep.so")
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+        raise RuntimeError("hipcc failed building %s" % os.path.basename(lib))
+    os.replace(lib + ".tmp", lib)
+    return lib
+
+
+def build(verbose: bool = False) -> str:
+    _hipcc(PROBE_SRC, PROBE_LIB, verbose)
+    return _hipcc(SRC, LIB, verbose)
 
 
 if __name__ == "__main__":

@@ -7,11 +7,12 @@ Usage:
 --trace: database of `rocprofv3 --kernel-trace --stats`; prints per-kernel calls,
 average and total duration.
 --fetch/--write: databases of `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE`
-runs of the same command.  The byte counters are calibrated against the device
-copy in the same run (bench.py --copy-calib copies 256 MiB with hipMemcpy,
-i.e. the runtime's copyBuffer kernel): scale = known bytes / counter bytes of
-that dispatch, per counter.  Per kernel class the calibrated bytes per dispatch
-are reported (words per cell when --cells is given).
+runs of the same command.  The byte counters are calibrated against the
+streaming probe's copy kernel in the same run (bench.py measures it in every
+run: k_copy4 reads and writes --copy-bytes bytes, one 4096 x 4096 float field
+by default): scale = known bytes / counter bytes of that dispatch, per
+counter.  Per kernel class the calibrated bytes per dispatch are reported
+(words per cell when --cells is given).
 """
 import argparse
 import hashlib
@@ -20,7 +21,7 @@ import os
 import sqlite3
 from collections import defaultdict
 
-COPY_BYTES = 64 * 1024 * 1024 * 4  # bench.py --copy-calib: 64 Mi floats
+COPY_BYTES = 4096 * 4096 * 4  # the probe copy of bench.py: one 4096 x 4096 float field each way
 
 
 def _q(db, sql, args=()):
@@ -47,16 +48,20 @@ def counter_values(db, counter):
     return out
 
 
-def calib(values):
-    copies = [v for k, vs in values.items() if "copyBuffer" in k for v in vs]
-    big = max(copies) if copies else 0.0
-    return COPY_BYTES / big if big > 0 else None
+def calib(values, copy_bytes):
+    """Scale of a byte counter: known bytes of the probe copy / its counter
+    bytes (the median over its dispatches)."""
+    copies = sorted(v for k, vs in values.items() if "k_copy4" in k for v in vs)
+    if not copies:
+        return None
+    mid = copies[len(copies) // 2]
+    return copy_bytes / mid if mid > 0 else None
 
 
 def short(name):
     """Kernel name without return type, namespace and parameter list."""
     n = name[5:] if name.startswith("void ") else name
-    return n.split("(")[0].replace("ws::", "")
+    return n.split("(")[0].replace("ws::", "").replace("(anonymous namespace)::", "")
 
 
 def source_hash(root):
@@ -99,6 +104,8 @@ def main():
     ap.add_argument("--fetch")
     ap.add_argument("--write")
     ap.add_argument("--cells", type=int, default=0)
+    ap.add_argument("--copy-bytes", type=int, default=COPY_BYTES,
+                    help="bytes the probe copy kernel reads (and writes) per dispatch")
     ap.add_argument("--out")
     ap.add_argument("--traffic-json")
     ap.add_argument("--command", default="")
@@ -118,12 +125,13 @@ def main():
     traffic = {}
     if a.fetch and a.write:
         fv, wv = counter_values(a.fetch, "FETCH_SIZE"), counter_values(a.write, "WRITE_SIZE")
-        fs, wsc = calib(fv), calib(wv)
+        fs, wsc = calib(fv, a.copy_bytes), calib(wv, a.copy_bytes)
         lines.append("")
         lines.append("HBM bytes per dispatch (FETCH_SIZE x %.3f, WRITE_SIZE x %.3f; factors from the "
-                     "%d-byte device copy)" % (fs or 0, wsc or 0, COPY_BYTES))
+                     "probe copy kernel, %d bytes each way)" % (fs or 0, wsc or 0, a.copy_bytes))
         for name in sorted(fv):
-            if "ws::" not in name.split("(")[0]:
+            head = name.split("(")[0]
+            if "ws::" not in head and "k_stream" not in head and "k_copy4" not in head:
                 continue
             rd = [v * fs for v in fv[name]][a.skip:]
             wr = [v * wsc for v in wv.get(name, [])][a.skip:]
@@ -145,15 +153,27 @@ def main():
         open(a.out, "w").write(text + "\n")
     names = a.kernel.split(",")
     if a.traffic_json and all(n in traffic for n in names):
-        # one kernel, or a group (the predictor and corrector stencils): the
-        # average over all dispatches of the group
+        # one kernel, or a group of kernels: the average over all dispatches
         root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
         n = sum(traffic[k]["dispatches"] for k in names)
         rd = sum(traffic[k]["read"] * traffic[k]["dispatches"] for k in names) / n
         wr = sum(traffic[k]["write"] * traffic[k]["dispatches"] for k in names) / n
-        json.dump({"kernel": a.kernel, "bytes_per_launch": rd + wr, "read": rd, "write": wr,
-                   "dispatches": n, "source_hash": source_hash(root), "command": a.command},
-                  open(a.traffic_json, "w"), indent=1)
+        out = {"kernel": a.kernel, "bytes_per_launch": rd + wr, "read": rd, "write": wr,
+               "dispatches": n, "source_hash": source_hash(root), "command": a.command}
+        if a.sq:
+            valu = sq_valu(a.sq)
+            if all(k in valu for k in names):
+                out["valu_lane_instr_per_launch"] = sum(valu[k] for k in names) / len(names)
+        json.dump(out, open(a.traffic_json, "w"), indent=1)
+
+
+def sq_valu(sq_db):
+    """Average VALU lane-instructions per dispatch of each kernel."""
+    per = defaultdict(list)
+    for name, counter, v in _q(sq_db, "select kernel_name, counter_name, value from counters_collection"):
+        if counter == "SQ_INSTS_VALU":
+            per[short(name)].append(float(v) * 64)
+    return {k: sum(v) / len(v) for k, v in per.items()}
 
 
 if __name__ == "__main__":

@@ -26,11 +26,13 @@ session's footprint.  A time-step change restarts the domain's multistep
 history and its step counter, so a session counts its steps from the
 checkpoint it was rolled back to (`base`).
 
-Reported: throughput, per-step latency seen by a session (tick wall time over
+Reported: throughput (all steps, and the steps run in the paper's BSNQ model
+only), the share of steps run degraded (NLSW after a rollback) and of steps
+undone by rollbacks, per-step latency seen by a session (tick wall time over
 the steps it made in that tick) at p50/p99, real-time ratio (simulated time
 over wall time while resident; sessions still resident at the end count with
-their time so far), queueing delay, and session counts (done, failed,
-recovered, rollbacks).
+their time so far), queueing delay, the largest footprint in use and queue
+length, and session counts (done, failed, recovered, rollbacks).
 """
 from __future__ import annotations
 
@@ -184,6 +186,10 @@ class Server:
         used = 0
         lat, lat_w, waits, rt_ratios = [], [], [], []
         cell_steps = 0
+        cell_steps_nlsw = 0                  # steps run degraded (NLSW at a reduced dt) after a rollback
+        session_steps = session_steps_nlsw = 0
+        cell_steps_discarded = 0             # steps undone by rollbacks
+        used_max = queue_max = 0
         done = rejected = admitted = ticks = failed = 0
         t0 = time.perf_counter()
         def arrivals():
@@ -218,6 +224,12 @@ class Server:
                 used += need
                 admitted += 1
                 waits.append(t_adm - arr)
+            nonlocal_max(used, len(queue))
+
+        def nonlocal_max(u, q):
+            nonlocal used_max, queue_max
+            used_max = max(used_max, u)
+            queue_max = max(queue_max, q)
 
         while True:
             if wall_limit is not None and time.perf_counter() - t0 >= wall_limit:
@@ -249,8 +261,13 @@ class Server:
                     lat.append(T / k)
                     lat_w.append(k)
                     cell_steps += k * s.work.cells
+                    session_steps += k
+                    if s.recoveries:
+                        cell_steps_nlsw += k * s.work.cells
+                        session_steps_nlsw += k
                 s.step = step
                 if health and s.recoveries < self.max_recoveries:   # roll back, go on in NLSW at dt/2
+                    cell_steps_discarded += (step - s.snap_step) * s.work.cells
                     s.step, s.next_edit = _recover(s, s.dom, s.edit_status)
                     self.recovered[s.rid] = s.recoveries
                     s.stop, s.next_edit = _next_stop(s.spec, s.step, s.next_edit)
@@ -295,7 +312,12 @@ class Server:
             "rollbacks": sum(self.recovered.values()),
             "sessions_resident_at_end": len(live), "sessions_queued_at_end": len(queue),
             "budget_bytes": self.budget,
+            "budget_used_max_bytes": used_max, "sessions_queued_max": queue_max,
             "throughput_cell_updates_per_s": cell_steps / wall if wall > 0 else 0.0,
+            "throughput_bsnq_cell_updates_per_s": (cell_steps - cell_steps_nlsw) / wall if wall > 0 else 0.0,
+            "degraded_share_of_session_steps": session_steps_nlsw / session_steps if session_steps else 0.0,
+            "degraded_share_of_cell_steps": cell_steps_nlsw / cell_steps if cell_steps else 0.0,
+            "discarded_share_of_cell_steps": cell_steps_discarded / cell_steps if cell_steps else 0.0,
             "step_latency_ms_p50": None if not lat else 1e3 * _pct(lat, lat_w, 50),
             "step_latency_ms_p99": None if not lat else 1e3 * _pct(lat, lat_w, 99),
             "queue_wait_s_p50": None if not waits else float(np.percentile(waits, 50)),
