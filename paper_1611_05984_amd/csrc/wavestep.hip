@@ -341,9 +341,9 @@ __global__ void k_check_dd(Dom d, int *flag) {
     };
     const float dc = dcell(i, j);
     float A, B, C;
-    tri_coef(d, dc, (dcell(i + 1, j) - dcell(i - 1, j)) * 0.5f * d.rdx, d.rdx, A, B, C);
+    tri_coef(d, tri_k(d.Bd, d.rdx), dc, dcell(i + 1, j) - dcell(i - 1, j), A, B, C);
     bool bad = !(fabsf(B) > fabsf(A) + fabsf(C));
-    tri_coef(d, dc, (dcell(i, j + 1) - dcell(i, j - 1)) * 0.5f * d.rdy, d.rdy, A, B, C);
+    tri_coef(d, tri_k(d.Bd, d.rdy), dc, dcell(i, j + 1) - dcell(i, j - 1), A, B, C);
     bad |= !(fabsf(B) > fabsf(A) + fabsf(C));
     if (bad) atomicOr(flag, 1);
 }
@@ -1003,6 +1003,16 @@ static void launch_pcr(int pnt, int nred, int nsys, hipStream_t st, const SolveA
     });
 }
 
+// The wave form of PCR (one wave per system, lane shuffles): equations per
+// lane the next power of two of nred / 64; systems of up to 512 unknowns.
+static bool pcrw_fits(int nred) { return nred <= 64 * PCRW_EPL_MAX; }
+static void launch_pcrw(int nred, int nsys, hipStream_t st, const SolveArgs &so) {
+    if (nred <= 64) hipLaunchKernelGGL(k_pcrw<1>, dim3(nsys), dim3(64), 0, st, so);
+    else if (nred <= 128) hipLaunchKernelGGL(k_pcrw<2>, dim3(nsys), dim3(64), 0, st, so);
+    else if (nred <= 256) hipLaunchKernelGGL(k_pcrw<4>, dim3(nsys), dim3(64), 0, st, so);
+    else hipLaunchKernelGGL(k_pcrw<8>, dim3(nsys), dim3(64), 0, st, so);
+}
+
 // One predictor or corrector pass: stencil, then the partitioned solves.
 // Arguments of pass p of a step.  cur: state buffer of the step's state;
 // sm: step index mod 3 (history slots); euler: one of the two start-up steps.
@@ -1118,6 +1128,8 @@ static void launch_reduced(const ws_domain *d, hipStream_t st, const SolveArgs &
     } else if (d->solver == WS_SOLVE_THOMAS) {
         const int waves = (d->g.ny + 63) / 64 + (d->g.nx + 63) / 64;
         hipLaunchKernelGGL(k_thomas, dim3(waves), dim3(64), 0, st, so);
+    } else if (d->solver == WS_SOLVE_PCR_WAVE) {
+        launch_pcrw(nred_of(d), d->g.ny + d->g.nx, st, so);
     } else {
         const int nred = d->nu > d->nv ? d->nu : d->nv;
         launch_pcr(d->pnt, nred, d->g.ny + d->g.nx, st, so);
@@ -1597,7 +1609,7 @@ static bool tuning_ok(const ws_tuning *t) {
     return t && (t->stencil_rows == 8 || t->stencil_rows == 16 || t->stencil_rows == 24 ||
                  t->stencil_rows == 32 || t->stencil_rows == 48 || t->stencil_rows == 64) &&
            (t->pcr_threads == 64 || t->pcr_threads == 128 || t->pcr_threads == 256) &&
-           (t->solver >= WS_SOLVE_PCR && t->solver <= WS_SOLVE_LU2) &&
+           (t->solver >= WS_SOLVE_PCR && t->solver <= WS_SOLVE_PCR_WAVE) &&
            (t->corrector_rows == 0 || t->corrector_rows == 8 || t->corrector_rows == 16 ||
             t->corrector_rows == 24 || t->corrector_rows == 32 || t->corrector_rows == 48 ||
             t->corrector_rows == 64);
@@ -1615,6 +1627,9 @@ extern "C" ws_status ws_get_tuning(const ws_domain *d, ws_tuning *out) {
 
 extern "C" ws_status ws_set_tuning(ws_domain *d, const ws_tuning *t) {
     if (!d || !tuning_ok(t)) return fail(WS_EINVAL, "ws_set_tuning: bad tuning");
+    if (t->solver == WS_SOLVE_PCR_WAVE && !pcrw_fits(nred_of(d)))
+        return fail(WS_EINVAL, "ws_set_tuning: reduced systems of %d unknowns are too long for the wave PCR (512)",
+                    nred_of(d));
     d->sy = t->stencil_rows;
     d->syc = t->corrector_rows == t->stencil_rows ? 0 : t->corrector_rows;
     d->pnt = t->pcr_threads;
@@ -1624,7 +1639,7 @@ extern "C" ws_status ws_set_tuning(ws_domain *d, const ws_tuning *t) {
 }
 
 extern "C" ws_status ws_batch_set_tuning(ws_batch *b, const ws_tuning *t) {
-    if (!b || !tuning_ok(t)) return fail(WS_EINVAL, "ws_batch_set_tuning: bad tuning");
+    if (!b || !tuning_ok(t) || t->solver == WS_SOLVE_PCR_WAVE) return fail(WS_EINVAL, "ws_batch_set_tuning: bad tuning");
     const int syc = t->corrector_rows == t->stencil_rows ? 0 : t->corrector_rows;
     if (b->sy != t->stencil_rows || b->syc != syc || b->pnt != t->pcr_threads || b->solver != t->solver) {
         b->sy = t->stencil_rows;
@@ -1751,6 +1766,16 @@ extern "C" ws_status ws_tune(ws_domain *d, const char *cache_path, void *stream,
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, e0, e1));
         if (ms < best_p) { best_p = ms; best.pcr_threads = threads[c]; best.solver = WS_SOLVE_PCR; }
+    }
+    if (pcrw_fits(nred)) {  // the wave form of PCR (same bits as the above)
+        launch_pcrw(nred, d->g.ny + d->g.nx, st, so);
+        HIPCHK(hipEventRecord(e0, st));
+        for (int k = 0; k < reps; ++k) launch_pcrw(nred, d->g.ny + d->g.nx, st, so);
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_p) { best_p = ms; best.solver = WS_SOLVE_PCR_WAVE; }
     }
     {
         const int waves = (d->g.ny + 63) / 64 + (d->g.nx + 63) / 64;

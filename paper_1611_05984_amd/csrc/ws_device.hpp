@@ -237,24 +237,30 @@ __device__ __forceinline__ void cu_flux(float g, float eps, float Df, const F3 &
     H2 = dry ? 0.f : t;
 }
 
-// Row/column system coefficients of eq. 23 for one cell.
-__device__ __forceinline__ void tri_coef_bsnq(float Bd, float dep, float ddep, float rh, float &A, float &B,
-                                              float &C) {
-    float al = (Bd + 1.f / 3.f) * dep * dep * rh * rh;
-    float be = dep * ddep * rh * (1.f / 6.f);
+// Row/column system coefficients of eq. 23 for one cell, from the cell's
+// still-water depth d and the difference dd = d_{+1} - d_{-1} of its two
+// neighbours along the direction (d_x = dd / (2 h)).  With the spacing h:
+// alpha = (B + 1/3) d^2 / h^2 and beta = d d_x / (6 h) = d dd / (12 h^2), and
+// A = beta - alpha, B = 1 + 2 alpha, C = -beta - alpha.  The constant
+// factors come premultiplied: kal = (B + 1/3) / h^2, kbe = 1 / (12 h^2).
+struct TriK { float kal, kbe; };
+__device__ __forceinline__ TriK tri_k(float Bd, float rh) { return {(Bd + 1.f / 3.f) * rh * rh, rh * rh * (1.f / 12.f)}; }
+__device__ __forceinline__ void tri_coef_bsnq(TriK k, float dep, float dd, float &A, float &B, float &C) {
+    const float al = k.kal * (dep * dep);
+    const float be = k.kbe * (dep * dd);
     A = be - al;
     B = 1.f + 2.f * al;
     C = -be - al;
 }
-__device__ __forceinline__ void tri_coef(const Dom &d, float dep, float ddep, float rh, float &A,
-                                         float &B, float &C) {
+__device__ __forceinline__ void tri_coef(const Dom &d, TriK k, float dep, float dd, float &A, float &B,
+                                         float &C) {
     if (d.model == NLSW) {
         A = 0.f;
         B = 1.f;
         C = 0.f;
         return;
     }
-    tri_coef_bsnq(d.Bd, dep, ddep, rh, A, B, C);
+    tri_coef_bsnq(k, dep, dd, A, B, C);
 }
 
 __device__ __forceinline__ float sponge_gamma(float dist, float Ls) {

@@ -41,11 +41,11 @@ struct StencilArgs {
     Dom d;
     const float *in;     // estimate read (the state itself for the predictor): eta, P, Q
     float *eout;         // new surface
-    float *rxy;          // U* - U*^n, V* - V*^n
-    float *h0;           // history level n (predictors write it): E, F, G, F*, G*
+    float *rxy;          // U* - U*^n, V* - V*^n, packed per cell
+    float *h0;           // history level n (predictors write it): (E, F, G), (F*, G*) packed
     const float *h1;     // level n-1
     const float *h2;     // level n-2
-    float *S;            // corrector bases: eta, U* and V* increments
+    float *S;            // corrector bases: eta, U* and V* increments, packed per cell
     unsigned fstride;    // bytes between consecutive fields of a group
     // grid-spacing factors of the difference formulas, premultiplied:
     // hx = 1/(2dx), sxx = 1/dx^2, cxy = 1/(4 dx dy), cxxx = 1/(2 dx^3),
@@ -112,6 +112,26 @@ __device__ __forceinline__ const float *ldp(const float *p, unsigned ob) {
     return reinterpret_cast<const float *>(reinterpret_cast<const char *>(p) + ob);
 }
 
+// Fields written and read together are packed per cell: a history level
+// holds (E, F, G) as three consecutive floats a cell, then (F*, G*) as two;
+// the corrector bases (eta, U* and V* increments) three; the solve's
+// right-hand sides (U* - U*^n, V* - V*^n) two.  A cell at float offset ob
+// (bytes) sits at 3 ob in a three-float group and at 2 ob in a two-float one,
+// so one 12- or 8-byte access replaces three or two field streams.
+struct f3 { float x, y, z; };
+__device__ __forceinline__ f3 ld3(const float *p, unsigned ob) {
+    return *reinterpret_cast<const f3 *>(reinterpret_cast<const char *>(p) + ob);
+}
+__device__ __forceinline__ void st3(float *p, unsigned ob, f3 v) {
+    *reinterpret_cast<f3 *>(reinterpret_cast<char *>(p) + ob) = v;
+}
+__device__ __forceinline__ float2 ld2(const float *p, unsigned ob) {
+    return *reinterpret_cast<const float2 *>(reinterpret_cast<const char *>(p) + ob);
+}
+__device__ __forceinline__ void st2(float *p, unsigned ob, float2 v) {
+    *reinterpret_cast<float2 *>(reinterpret_cast<char *>(p) + ob) = v;
+}
+
 // Rows per stencil strip: a template parameter (8, 16, 24, 32, 48 or 64)
 // chosen per grid shape; taller strips spend less on the 4 warm-up rows,
 // shorter ones give more workgroups.
@@ -154,7 +174,7 @@ __device__ __forceinline__ void stencil_body(const StencilArgs &A, int bx, int b
     float Hs0 = 0.f, Hs1 = 0.f, Hs2 = 0.f;                   // flux through the south face of row r-2
     float Dcm = 0.f, Dc0 = 0.f;                              // cell depth D of rows r-3, r-2
 
-    const unsigned F1 = A.fstride, F2 = 2u * A.fstride, F3b = 3u * A.fstride, F4 = 4u * A.fstride;
+    const unsigned F1 = A.fstride, F2 = 2u * A.fstride, F3b = 3u * A.fstride;
     const float *pin = ldp(A.in, F1), *qin = ldp(A.in, F2);
     // row r + 1 is loaded while row r is computed
     float ne = 0.f, np = 0.f, nq = 0.f, nhe = 0.f, nhp = 0.f, nhq = 0.f, nDl = 0.f, nDr = 0.f;
@@ -221,12 +241,18 @@ __device__ __forceinline__ void stencil_body(const StencilArgs &A, int bx, int b
             float Fs2v = 0.f, Gs2v = 0.f, Sev = 0.f, SUv = 0.f, SVv = 0.f;
             if (out) {
                 if (kind == 1) {
-                    E1v = ldo(A.h1, o); F1v = ldo(A.h1, o + F1); G1v = ldo(A.h1, o + F2);
-                    Fs1v = ldo(A.h1, o + F3b); Gs1v = ldo(A.h1, o + F4);
-                    E2v = ldo(A.h2, o); F2v = ldo(A.h2, o + F1); G2v = ldo(A.h2, o + F2);
-                    if (A.x2 != 0.f) { Fs2v = ldo(A.h2, o + F3b); Gs2v = ldo(A.h2, o + F4); }
+                    const f3 l1 = ld3(A.h1, 3u * o), l2 = ld3(A.h2, 3u * o);
+                    const float2 s1 = ld2(A.h1, F3b + 2u * o);
+                    E1v = l1.x; F1v = l1.y; G1v = l1.z;
+                    Fs1v = s1.x; Gs1v = s1.y;
+                    E2v = l2.x; F2v = l2.y; G2v = l2.z;
+                    if (A.x2 != 0.f) {
+                        const float2 s2 = ld2(A.h2, F3b + 2u * o);
+                        Fs2v = s2.x; Gs2v = s2.y;
+                    }
                 } else if (kind == 2) {
-                    Sev = ldo(A.S, o); SUv = ldo(A.S, o + F1); SVv = ldo(A.S, o + F2);
+                    const f3 sb = ld3(A.S, 3u * o);
+                    Sev = sb.x; SUv = sb.y; SVv = sb.z;
                 }
             }
             // cell and face still-water depths
@@ -294,11 +320,10 @@ __device__ __forceinline__ void stencil_body(const StencilArgs &A, int bx, int b
                     V = dt * G;
                 } else if (kind == 1) {
                     const float c12 = dt * (1.f / 12.f), c24 = dt * (1.f / 24.f);
-                    if (A.write_S) {
-                        sto(A.S, o, e2 + c24 * (19.f * E - 5.f * E1v + E2v));
-                        sto(A.S, o + F1, c24 * (19.f * F - 5.f * F1v + F2v) - Fs);
-                        sto(A.S, o + F2, c24 * (19.f * G - 5.f * G1v + G2v) - Gs);
-                    }
+                    if (A.write_S)
+                        st3(A.S, 3u * o, f3{e2 + c24 * (19.f * E - 5.f * E1v + E2v),
+                                            c24 * (19.f * F - 5.f * F1v + F2v) - Fs,
+                                            c24 * (19.f * G - 5.f * G1v + G2v) - Gs});
                     en = e2 + c12 * (23.f * E - 16.f * E1v + 5.f * E2v);
                     U = c12 * (23.f * F - 16.f * F1v + 5.f * F2v) + (A.x0 * Fs + A.x1 * Fs1v + A.x2 * Fs2v);
                     V = c12 * (23.f * G - 16.f * G1v + 5.f * G2v) + (A.x0 * Gs + A.x1 * Gs1v + A.x2 * Gs2v);
@@ -309,15 +334,11 @@ __device__ __forceinline__ void stencil_body(const StencilArgs &A, int bx, int b
                     V = SVv + c9 * G + Gs;
                 }
                 if (kind != 2) {
-                    sto(A.h0, o, E);
-                    sto(A.h0, o + F1, F);
-                    sto(A.h0, o + F2, G);
-                    sto(A.h0, o + F3b, Fs);
-                    sto(A.h0, o + F4, Gs);
+                    st3(A.h0, 3u * o, f3{E, F, G});
+                    st2(A.h0, F3b + 2u * o, make_float2(Fs, Gs));
                 }
                 sto(A.eout, o, fmaxf(en, -Dc));
-                sto(A.rxy, o, U);
-                sto(A.rxy, o + F1, V);
+                st2(A.rxy, 2u * o, make_float2(U, V));
             }
         }
         hiy_prev = hiy;
@@ -368,7 +389,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 // ------------------------------------------------------------- solver parts
 struct SolveArgs {
     Dom d;
-    float *rx, *ry;            // right-hand sides (read by the reduction and the expansion)
+    float *rx, *ry;            // right-hand sides (read by the reduction and the expansion):
+                               // the pair packed per cell from rx on (ry: its second field)
     float4 *redx, *redy;       // reduced equations (sub, diag, super, rhs) per unknown
     float *solx, *soly;        // reduced solutions
     // layout 1 (factored solve): the reduced right-hand sides (in the memory of
@@ -417,8 +439,9 @@ __device__ __forceinline__ void stage_tile(const SolveArgs &A, SolveTile &s, int
     for (int m = 0; m < CPT; ++m) {
         const int k = tid + m * T, cx = k % TX, cy = k / TX;
         const size_t o = (size_t)(j0 + cy) * d.pitch + i0 + cx;
-        vx[m] = A.rx[o];
-        vy[m] = A.ry[o];
+        const float2 v = reinterpret_cast<const float2 *>(A.rx)[o];  // (U* - U*^n, V* - V*^n) of the cell
+        vx[m] = v.x;
+        vy[m] = v.y;
     }
 #pragma unroll
     for (int m = 0; m < ZPT; ++m) {
@@ -463,15 +486,14 @@ __device__ __forceinline__ void seg_coefs(const SolveArgs &A, const SolveTile &s
     const int fi = i0 + x0, fj = j0 + y0;
     const bool inner = INNER && d.model != NLSW &&
                        (dir == 0 ? fj < d.ny && fi >= 1 && fi + M <= d.nx - 1 : fi < d.nx && fj >= 1 && fj + M <= d.ny - 1);
+    const TriK tk = tri_k(d.Bd, dir == 0 ? d.rdx : d.rdy);
     if (inner) {
-        const float rh = dir == 0 ? d.rdx : d.rdy;
 #pragma unroll
         for (int k = 0; k < M; ++k) {
             const int cx = dir == 0 ? x0 + k : x0, cy = dir == 0 ? y0 : y0 + k;
             const float dep = s.dc[cy + 1][cx + 1];
-            const float dd = dir == 0 ? (s.dc[cy + 1][cx + 2] - s.dc[cy + 1][cx]) * 0.5f * rh
-                                      : (s.dc[cy + 2][cx + 1] - s.dc[cy][cx + 1]) * 0.5f * rh;
-            tri_coef_bsnq(d.Bd, dep, dd, rh, a[k], b[k], c[k]);
+            const float dd = dir == 0 ? s.dc[cy + 1][cx + 2] - s.dc[cy + 1][cx] : s.dc[cy + 2][cx + 1] - s.dc[cy][cx + 1];
+            tri_coef_bsnq(tk, dep, dd, a[k], b[k], c[k]);
         }
         return;
     }
@@ -483,8 +505,7 @@ __device__ __forceinline__ void seg_coefs(const SolveArgs &A, const SolveTile &s
         if (i < d.nx && j < d.ny) {
             const float dep = s.dc[cy + 1][cx + 1];
             if (dir == 0) {
-                const float dd = (s.dc[cy + 1][cx + 2] - s.dc[cy + 1][cx]) * 0.5f * d.rdx;
-                tri_coef(d, dep, dd, d.rdx, aa, bb, cc);
+                tri_coef(d, tk, dep, s.dc[cy + 1][cx + 2] - s.dc[cy + 1][cx], aa, bb, cc);
                 if (i == 0) {
                     if (is_wall(d, 0)) bb -= aa;
                     else if (r) r[k * st] -= aa * ghost_change(A, 0, j + 2, 1);
@@ -496,8 +517,7 @@ __device__ __forceinline__ void seg_coefs(const SolveArgs &A, const SolveTile &s
                     cc = 0.f;
                 }
             } else {
-                const float dd = (s.dc[cy + 2][cx + 1] - s.dc[cy][cx + 1]) * 0.5f * d.rdy;
-                tri_coef(d, dep, dd, d.rdy, aa, bb, cc);
+                tri_coef(d, tk, dep, s.dc[cy + 2][cx + 1] - s.dc[cy][cx + 1], aa, bb, cc);
                 if (j == 0) {
                     if (is_wall(d, 2)) bb -= aa;
                     else if (r) r[k * st] -= aa * ghost_change(A, 2, i + 2, 2);
@@ -1063,6 +1083,13 @@ __global__ __launch_bounds__(64) void k_lu2_solve(SolveArgs A) { lu2_solve_body(
 // two, PNT * EPL >= N) equations per thread at most, so the register array
 // is sized for the actual systems.
 constexpr int PCR_NT = 128;  // default
+// One PCR level for equation e with its neighbours m (stride below) and p
+// (stride above), identity rows standing in past the system's ends: both
+// PCR forms call it, so they give the same bits.
+__device__ __forceinline__ float4 pcr_combine(float4 e, float4 m, float4 p) {
+    const float al = -e.x * frcp(m.y), ga = -e.z * frcp(p.y);
+    return make_float4(al * m.x, e.y + al * m.z + ga * p.x, ga * p.z, e.w + al * m.w + ga * p.w);
+}
 // One reduced system of N equations (sub, diag, super, rhs) from src; solutions to dst.
 template <int PNT, int PCR_EPL>
 __device__ __forceinline__ void pcr_solve(int N, const float4 *src, float *dst, float4 *buf) {
@@ -1085,8 +1112,7 @@ __device__ __forceinline__ void pcr_solve(int N, const float4 *src, float *dst, 
                 const float4 e = eq[j];
                 const float4 m = k - st >= 0 ? buf[k - st] : id;
                 const float4 p = k + st < N ? buf[k + st] : id;
-                const float al = -e.x * frcp(m.y), ga = -e.z * frcp(p.y);
-                eq[j] = make_float4(al * m.x, e.y + al * m.z + ga * p.x, ga * p.z, e.w + al * m.w + ga * p.w);
+                eq[j] = pcr_combine(e, m, p);
             }
         __syncthreads();
 #pragma unroll
@@ -1097,6 +1123,94 @@ __device__ __forceinline__ void pcr_solve(int N, const float4 *src, float *dst, 
 #pragma unroll
     for (int j = 0; j < PCR_EPL; ++j)
         if (j < nmine) dst[tid + j * PNT] = eq[j].w / eq[j].y;
+}
+
+// PCR of one reduced system on a single wave, with no LDS array and no
+// barrier: equation k = lane + 64 j sits in register j of its lane.  At a
+// level of stride st < 64 the neighbours k - st and k + st are in lane
+// (lane -+ st) mod 64, register j or the next one out, and come by lane
+// shuffles (ds_bpermute); at st >= 64 they are the lane's own registers
+// j -+ st / 64.  The levels are unrolled, so every register index is a
+// compile-time constant.  Systems of up to 64 EPL unknowns.
+__device__ __forceinline__ float4 shfl4(float4 v, int src) {
+    return make_float4(__shfl(v.x, src), __shfl(v.y, src), __shfl(v.z, src), __shfl(v.w, src));
+}
+// Component-wise choice between two equations (a select of values: a ?: on
+// the vectors themselves can become a select of addresses, which puts the
+// register arrays in scratch memory).
+__device__ __forceinline__ float4 sel4(bool c, float4 a, float4 b) {
+    return make_float4(c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z, c ? a.w : b.w);
+}
+// One level (stride 2^LV) of the wave form, for every equation of the lane.
+// Below stride 64 every neighbour is fetched by shuffles before any equation
+// changes, so the update runs in place; from 64 on the neighbours are the
+// lane's own registers and the new equations go to a fresh array first.
+template <int EPL, int LV>
+__device__ __forceinline__ void pcrw_level(int N, int lane, float4 (&eq)[EPL]) {
+    constexpr int st = 1 << LV;
+    const float4 id = make_float4(0.f, 1.f, 0.f, 0.f);
+    if constexpr (st < 64) {
+        const int up = (lane + st) & 63, dn = (lane - st) & 63;
+        float4 su[EPL], sd[EPL];  // equation j of lane up, of lane dn
+#pragma unroll
+        for (int j = 0; j < EPL; ++j) {
+            su[j] = shfl4(eq[j], up);
+            sd[j] = shfl4(eq[j], dn);
+        }
+#pragma unroll
+        for (int j = 0; j < EPL; ++j) {
+            const int k = lane + 64 * j;
+            const float4 hi = sel4(lane + st < 64, su[j], j + 1 < EPL ? su[j + 1] : id);
+            const float4 lo = sel4(lane >= st, sd[j], j > 0 ? sd[j - 1] : id);
+            eq[j] = pcr_combine(eq[j], sel4(k - st >= 0, lo, id), sel4(k + st < N, hi, id));
+        }
+    } else {
+        constexpr int q = st / 64;
+        float4 nw[EPL];
+#pragma unroll
+        for (int j = 0; j < EPL; ++j) {
+            const int k = lane + 64 * j;
+            const float4 hi = j + q < EPL ? eq[j + q] : id, lo = j >= q ? eq[j - q] : id;
+            nw[j] = pcr_combine(eq[j], sel4(k - st >= 0, lo, id), sel4(k + st < N, hi, id));
+        }
+#pragma unroll
+        for (int j = 0; j < EPL; ++j) eq[j] = nw[j];
+    }
+}
+template <int EPL, int LV>
+__device__ __forceinline__ void pcrw_levels(int N, int lane, float4 (&eq)[EPL]) {
+    if constexpr ((1 << LV) < 64 * EPL) {
+        if ((1 << LV) < N) {
+            pcrw_level<EPL, LV>(N, lane, eq);
+            pcrw_levels<EPL, LV + 1>(N, lane, eq);
+        }
+    }
+}
+template <int EPL>
+__device__ __forceinline__ void pcrw_solve(int N, const float4 *src, float *dst) {
+    const int lane = threadIdx.x & 63;
+    const float4 id = make_float4(0.f, 1.f, 0.f, 0.f);
+    float4 eq[EPL];
+#pragma unroll
+    for (int j = 0; j < EPL; ++j) {
+        const int k = lane + 64 * j;
+        eq[j] = sel4(k < N, src[k < N ? k : 0], id);
+    }
+    pcrw_levels<EPL, 0>(N, lane, eq);
+#pragma unroll
+    for (int j = 0; j < EPL; ++j) {
+        const int k = lane + 64 * j;
+        if (k < N) dst[k] = eq[j].w / eq[j].y;
+    }
+}
+constexpr int PCRW_EPL_MAX = 8;  // the wave form takes systems of up to 512 unknowns
+
+template <int EPL>
+__global__ __launch_bounds__(64) void k_pcrw(SolveArgs A) {
+    const Dom &d = A.d;
+    const int sys = blockIdx.x;
+    if (sys < d.ny) pcrw_solve<EPL>(d.nu, A.redx + (size_t)sys * d.nu, A.solx + (size_t)sys * d.nu);
+    else pcrw_solve<EPL>(d.nv, A.redy + (size_t)(sys - d.ny) * d.nv, A.soly + (size_t)(sys - d.ny) * d.nv);
 }
 
 // System sys: rows 0..ny-1 (x direction), then columns.

@@ -24,7 +24,7 @@ SOLID, SPONGE, WAVES = 0, 1, 2
 EDIT_WATER, EDIT_TERRAIN = 0, 1
 READ_W, READ_H = 0, 1
 STATIC_WORKSPACE_BYTES = 80 << 20      # WS_STATIC_WORKSPACE_BYTES of the C header
-SOLVE_PCR, SOLVE_THOMAS, SOLVE_LU, SOLVE_LU2 = 0, 1, 2, 3
+SOLVE_PCR, SOLVE_THOMAS, SOLVE_LU, SOLVE_LU2, SOLVE_PCR_WAVE = 0, 1, 2, 3, 4
 K_PREDICTOR, K_CORRECTOR, K_REDUCE, K_SOLVE, K_EXPAND, K_COUNT = 0, 1, 2, 3, 4, 5
 KERNEL_NAMES = ("k_stencil[predictor]", "k_stencil[corrector]", "k_reduce", "reduced_solve", "k_expand")
 

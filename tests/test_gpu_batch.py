@@ -278,7 +278,7 @@ def test_tunings_identical_results_and_autotuner(tmp_path):
     before = d.state_numpy()
     cache = str(tmp_path / "tune.txt")
     t = d.tune(cache)
-    assert t[0] in (8, 16, 24, 32, 48, 64) and t[1] in (64, 128, 256) and t[2] in (0, 1, 2, 3)
+    assert t[0] in (8, 16, 24, 32, 48, 64) and t[1] in (64, 128, 256) and t[2] in (0, 1, 2, 3, 4)
     assert t[3] in (0, 8, 16, 24, 32, 48, 64) and t[3] != t[0]
     assert d.tuning() == t
     after = d.state_numpy()
@@ -342,6 +342,34 @@ def test_tunings_identical_results_and_autotuner(tmp_path):
     same(tw, twb, "batched two-ended factored solve")
     for x, y in zip(lu2.state_numpy(), tw.state_numpy()):
         assert np.abs(x - y).max() <= 1e-6 * max(1.0, np.abs(x).max())
+    B.close()
+
+
+@pytest.mark.parametrize("nx,ny", [(300, 150), (90, 40), (1000, 100), (1030, 520), (2050, 300), (4096, 64)])
+def test_wave_pcr_equals_lds_pcr(nx, ny):
+    """PCR on one wave per system (lane shuffles, no LDS array, no barrier)
+    gives the bits of the workgroup PCR: reduced systems of 2 x 19 .. 512
+    unknowns (every equations-per-lane variant, ragged against the wave),
+    over Euler, predictor and corrector passes.  Longer systems are refused
+    for it, and so is a batch."""
+    ws = _ws()
+    w = wl.config2(nx=nx, ny=ny, seed=13)
+    say("case: wave PCR vs workgroup PCR on %s" % w.name)
+    a, b = make(w), make(w)
+    a.set_tuning(16, 128, ws.SOLVE_PCR)
+    b.set_tuning(16, 128, ws.SOLVE_PCR_WAVE)
+    assert b.tuning()[2] == ws.SOLVE_PCR_WAVE
+    for n in (2, 1, 9):
+        a.advance(n)
+        b.advance(n)
+        same(a, b, "wave PCR after %d steps" % a.query()[0])
+    big = make(wl.config1(nx=4100, ny=16))          # row systems of 2 x 257 unknowns
+    with pytest.raises(ws.WaveStepError) as e:
+        big.set_tuning(16, 128, ws.SOLVE_PCR_WAVE)
+    assert e.value.status == ws.EINVAL
+    B = ws.Batch(2)
+    with pytest.raises(ws.WaveStepError):
+        B.set_tuning(16, 128, ws.SOLVE_PCR_WAVE)
     B.close()
 
 
