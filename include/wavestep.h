@@ -332,9 +332,12 @@ ws_status ws_corrector_stats(const ws_domain *d, int32_t *last, int64_t *total, 
  * (WS_SOLVE_PCR_WAVE: each lane holds equations k = lane + 64 j; the levels
  * of stride below 64 exchange equations by lane shuffles, the longer ones
  * within a lane's registers; no LDS array and no barrier; reduced systems of
- * up to 512 unknowns, i.e. grids up to 4096 cells in a direction
- * (WS_EINVAL otherwise); single domains only, ws_batch_set_tuning refuses
- * it).  Rows and threads do not change results (bitwise); THOMAS and LU give
+ * up to 512 unknowns, i.e. grids up to 4096 cells in a direction:
+ * ws_set_tuning returns WS_EINVAL for longer ones, and a batch whose largest
+ * system is longer runs the workgroup PCR instead, which gives the same
+ * bits).  The autotuners time each strategy together with the reduction it
+ * needs (the factored solves' reduction writes right-hand sides only).
+ * Rows and threads do not change results (bitwise); THOMAS and LU give
  * the same bits, and so do PCR and PCR_WAVE; PCR, LU and LU2 round the
  * reduced solve differently. */
 enum { WS_SOLVE_PCR = 0, WS_SOLVE_THOMAS = 1, WS_SOLVE_LU = 2, WS_SOLVE_LU2 = 3,  /* reduced-system strategy */

@@ -1013,6 +1013,14 @@ static void launch_pcrw(int nred, int nsys, hipStream_t st, const SolveArgs &so)
     else hipLaunchKernelGGL(k_pcrw<8>, dim3(nsys), dim3(64), 0, st, so);
 }
 
+static void launch_pcrw_batch(int nred, dim3 pg, hipStream_t st, const BatchDesc *desc, const BatchState *state,
+                              const int *pre, int n, int p) {
+    if (nred <= 64) hipLaunchKernelGGL(kb_pcrw<1>, pg, dim3(64), 0, st, desc, state, pre, n, p);
+    else if (nred <= 128) hipLaunchKernelGGL(kb_pcrw<2>, pg, dim3(64), 0, st, desc, state, pre, n, p);
+    else if (nred <= 256) hipLaunchKernelGGL(kb_pcrw<4>, pg, dim3(64), 0, st, desc, state, pre, n, p);
+    else hipLaunchKernelGGL(kb_pcrw<8>, pg, dim3(64), 0, st, desc, state, pre, n, p);
+}
+
 // One predictor or corrector pass: stencil, then the partitioned solves.
 // Arguments of pass p of a step.  cur: state buffer of the step's state;
 // sm: step index mod 3 (history slots); euler: one of the two start-up steps.
@@ -1404,8 +1412,9 @@ static ws_status batch_upload(ws_batch *b) {
         pre[4][k + 1] = pre[4][k] + (int)(sgc.x * sgc.y);
         pre[2][k + 1] = pre[2][k] + (b->solver == WS_SOLVE_LU2                     ? solve2_waves(D.d.nx, D.d.ny)
                                      : b->solver == WS_SOLVE_LU && luw_waves(nred) ? luw_groups(D.d.nx, D.d.ny)
-                                     : b->solver != WS_SOLVE_PCR                   ? (D.d.ny + 63) / 64 + (D.d.nx + 63) / 64
-                                                                                   : D.nsys);
+                                     : b->solver != WS_SOLVE_PCR && b->solver != WS_SOLVE_PCR_WAVE
+                                         ? (D.d.ny + 63) / 64 + (D.d.nx + 63) / 64
+                                         : D.nsys);
         pre[3][k + 1] = pre[3][k] + (D.makers ? (8 * D.d.gl * GHL + 255) / 256 : 0);
         maxK = D.K > maxK ? D.K : maxK;
     }
@@ -1455,6 +1464,8 @@ static ws_status batch_step(ws_batch *b, hipStream_t st) {
                 hipLaunchKernelGGL(kb_lu_solve, pg, dim3(64), 0, st, b->d_desc, b->d_state, b->d_pre[2], n, p);
         else if (b->solver == WS_SOLVE_THOMAS)
             hipLaunchKernelGGL(kb_thomas, pg, dim3(64), 0, st, b->d_desc, b->d_state, b->d_pre[2], n, p);
+        else if (b->solver == WS_SOLVE_PCR_WAVE && pcrw_fits(b->nred))  // (longer: the workgroup PCR, same bits)
+            launch_pcrw_batch(b->nred, pg, st, b->d_desc, b->d_state, b->d_pre[2], n, p);
         else
             pcr_dispatch(b->pnt, pcr_epl(b->pnt, b->nred), [&](auto shape) {
                 using S = decltype(shape);
@@ -1639,7 +1650,7 @@ extern "C" ws_status ws_set_tuning(ws_domain *d, const ws_tuning *t) {
 }
 
 extern "C" ws_status ws_batch_set_tuning(ws_batch *b, const ws_tuning *t) {
-    if (!b || !tuning_ok(t) || t->solver == WS_SOLVE_PCR_WAVE) return fail(WS_EINVAL, "ws_batch_set_tuning: bad tuning");
+    if (!b || !tuning_ok(t)) return fail(WS_EINVAL, "ws_batch_set_tuning: bad tuning");
     const int syc = t->corrector_rows == t->stencil_rows ? 0 : t->corrector_rows;
     if (b->sy != t->stencil_rows || b->syc != syc || b->pnt != t->pcr_threads || b->solver != t->solver) {
         b->sy = t->stencil_rows;
@@ -1752,92 +1763,58 @@ extern "C" ws_status ws_tune(ws_domain *d, const char *cache_path, void *stream,
         best.stencil_rows = rows[cp];
         best.corrector_rows = rows[cc];
     }
-    // the reduced systems need valid equations: one reduction of the increments
-    so.layout = 0;
-    hipLaunchKernelGGL(k_reduce, tiles(d), dim3(NT), 0, st, so);
+    // Reduced-system strategies, each timed as the reduction (whose layout and
+    // writes depend on the strategy: reduced equations, or right-hand sides
+    // only for the factored solves) followed by the solve, `reps` times.
     const int nred = d->nu > d->nv ? d->nu : d->nv;
     const int threads[3] = {64, 128, 256};
+    auto time_pairs = [&](const SolveArgs &sx, auto &&solve) -> float {
+        hipLaunchKernelGGL(k_reduce, tiles(d), dim3(NT), 0, st, sx);  // warm-up
+        solve();
+        float total = 0.f;
+        for (int k = 0; k < reps; ++k) {
+            (void)hipEventRecord(e0, st);
+            hipLaunchKernelGGL(k_reduce, tiles(d), dim3(NT), 0, st, sx);
+            solve();
+            (void)hipEventRecord(e1, st);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            total += ms;
+        }
+        return total;
+    };
+    so.layout = 0;
     for (int c = 0; c < 3; ++c) {
-        launch_pcr(threads[c], nred, d->g.ny + d->g.nx, st, so);
-        HIPCHK(hipEventRecord(e0, st));
-        for (int k = 0; k < reps; ++k) launch_pcr(threads[c], nred, d->g.ny + d->g.nx, st, so);
-        HIPCHK(hipEventRecord(e1, st));
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        const float ms = time_pairs(so, [&] { launch_pcr(threads[c], nred, d->g.ny + d->g.nx, st, so); });
         if (ms < best_p) { best_p = ms; best.pcr_threads = threads[c]; best.solver = WS_SOLVE_PCR; }
     }
     if (pcrw_fits(nred)) {  // the wave form of PCR (same bits as the above)
-        launch_pcrw(nred, d->g.ny + d->g.nx, st, so);
-        HIPCHK(hipEventRecord(e0, st));
-        for (int k = 0; k < reps; ++k) launch_pcrw(nred, d->g.ny + d->g.nx, st, so);
-        HIPCHK(hipEventRecord(e1, st));
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        const float ms = time_pairs(so, [&] { launch_pcrw(nred, d->g.ny + d->g.nx, st, so); });
         if (ms < best_p) { best_p = ms; best.solver = WS_SOLVE_PCR_WAVE; }
     }
     {
-        const int waves = (d->g.ny + 63) / 64 + (d->g.nx + 63) / 64;
-        hipLaunchKernelGGL(k_reduce, tiles(d), dim3(NT), 0, st, so);  // the sweep overwrites the equations
-        hipLaunchKernelGGL(k_thomas, dim3(waves), dim3(64), 0, st, so);
-        float total = 0.f;
-        for (int k = 0; k < reps; ++k) {
-            hipLaunchKernelGGL(k_reduce, tiles(d), dim3(NT), 0, st, so);
-            HIPCHK(hipEventRecord(e0, st));
-            hipLaunchKernelGGL(k_thomas, dim3(waves), dim3(64), 0, st, so);
-            HIPCHK(hipEventRecord(e1, st));
-            HIPCHK(hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-            total += ms;
-        }
-        if (total < best_p) { best_p = total; best.solver = WS_SOLVE_THOMAS; }
+        const int waves = (d->g.ny + 63) / 64 + (d->g.nx + 63) / 64;  // the sweep overwrites the equations
+        const float ms = time_pairs(so, [&] { hipLaunchKernelGGL(k_thomas, dim3(waves), dim3(64), 0, st, so); });
+        if (ms < best_p) { best_p = ms; best.solver = WS_SOLVE_THOMAS; }
     }
     {
-        // factored solve: factors once (kept: they match the domain's current
+        // factored solves: factors once (kept: they match the domain's current
         // bathymetry and boundaries), then only the right-hand-side sweeps
         const int keep = d->solver;
-        d->solver = WS_SOLVE_LU;
-        ws_status r = ensure_factors(d, st);
-        if (r != WS_OK) {
-            d->solver = keep;
-            return r;
-        }
         SolveArgs s1 = so;
         s1.layout = 1;
-        float total = 0.f;
-        for (int k = 0; k < reps; ++k) {
-            hipLaunchKernelGGL(k_reduce, tiles(d), dim3(NT), 0, st, s1);
-            HIPCHK(hipEventRecord(e0, st));
-            launch_reduced(d, st, s1);
-            HIPCHK(hipEventRecord(e1, st));
-            HIPCHK(hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-            total += ms;
-        }
-        if (total < best_p) { best_p = total; best.solver = WS_SOLVE_LU; }
-        // two-ended factored solve
-        d->solver = WS_SOLVE_LU2;
-        r = ensure_factors(d, st);
-        if (r != WS_OK) {
-            d->solver = keep;
-            return r;
-        }
-        total = 0.f;
-        for (int k = 0; k < reps; ++k) {
-            hipLaunchKernelGGL(k_reduce, tiles(d), dim3(NT), 0, st, s1);
-            HIPCHK(hipEventRecord(e0, st));
-            hipLaunchKernelGGL(k_lu2_solve, dim3(solve2_waves(d->g.nx, d->g.ny)), dim3(64), 0, st, s1);
-            HIPCHK(hipEventRecord(e1, st));
-            HIPCHK(hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-            total += ms;
+        for (int sv : {WS_SOLVE_LU, WS_SOLVE_LU2}) {
+            d->solver = sv;
+            ws_status r = ensure_factors(d, st);
+            if (r != WS_OK) {
+                d->solver = keep;
+                return r;
+            }
+            const float ms = time_pairs(s1, [&] { launch_reduced(d, st, s1); });
+            if (ms < best_p) { best_p = ms; best.solver = sv; }
         }
         d->solver = keep;
-        if (total < best_p) { best_p = total; best.solver = WS_SOLVE_LU2; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1922,9 +1899,14 @@ extern "C" ws_status ws_batch_tune(ws_batch *b, void *stream, ws_tuning *out) {
     const int n = (int)b->order.size();
     best = 1e30f;
     if (n > 0) {
-        hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NTB), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, 1);
+        // each strategy timed as the reduction (its layout depends on the
+        // strategy) followed by the reduced solve
+        auto reduce = [&] {
+            hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NTB), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, 1);
+        };
         for (int c = 0; c < 3; ++c) {
             const float ms = time_it([&] {
+                reduce();
                 const dim3 pg(b->total[2]);
                 const size_t shm = sizeof(float4) * b->nred;
                 pcr_dispatch(threads[c], pcr_epl(threads[c], b->nred), [&](auto shape) {
@@ -1935,14 +1917,21 @@ extern "C" ws_status ws_batch_tune(ws_batch *b, void *stream, ws_tuning *out) {
             });
             if (ms < best) { best = ms; best_pnt = threads[c]; }
         }
+        if (pcrw_fits(b->nred)) {  // the wave form of PCR (the PCR prefix table)
+            const float ms = time_it([&] {
+                reduce();
+                launch_pcrw_batch(b->nred, dim3(b->total[2]), st, b->d_desc, b->d_state, b->d_pre[2], n, 1);
+            });
+            if (ms < best) { best = ms; best_solver = WS_SOLVE_PCR_WAVE; }
+        }
         // lane-per-system Thomas (its prefix table differs: rebuilt for the trial)
         b->solver = WS_SOLVE_THOMAS;  // trial
         b->dirty = true;
         if ((r = batch_upload(b)) != WS_OK) return r;
         float total = 0.f;
         for (int k = 0; k < 4; ++k) {
-            hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NTB), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, 1);
             (void)hipEventRecord(e0, st);
+            reduce();
             hipLaunchKernelGGL(kb_thomas, dim3(b->total[2]), dim3(64), 0, st, b->d_desc, b->d_state, b->d_pre[2], n, 1);
             (void)hipEventRecord(e1, st);
             (void)hipEventSynchronize(e1);
@@ -1950,8 +1939,10 @@ extern "C" ws_status ws_batch_tune(ws_batch *b, void *stream, ws_tuning *out) {
             (void)hipEventElapsedTime(&ms, e0, e1);
             if (k > 0) total += ms;
         }
-        best_solver = total < best ? WS_SOLVE_THOMAS : WS_SOLVE_PCR;
-        if (total < best) best = total;
+        if (total < best) {
+            best = total;
+            best_solver = WS_SOLVE_THOMAS;
+        }
         // factored solve: argument blocks with the interleaved layout, factors
         b->solver = WS_SOLVE_LU;  // trial
         b->dirty = true;
@@ -1960,8 +1951,8 @@ extern "C" ws_status ws_batch_tune(ws_batch *b, void *stream, ws_tuning *out) {
             if ((r = ensure_factors(b->slots[sl], st)) != WS_OK) return r;
         total = 0.f;
         for (int k = 0; k < 4; ++k) {
-            hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NTB), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, 1);
             (void)hipEventRecord(e0, st);
+            reduce();
             if (const int G = luw_waves(b->nred))
                 hipLaunchKernelGGL(kb_luw_solve, dim3(b->total[2]), dim3(64 * G), 0, st, b->d_desc, b->d_state,
                                    b->d_pre[2], n, 1);
@@ -1985,8 +1976,8 @@ extern "C" ws_status ws_batch_tune(ws_batch *b, void *stream, ws_tuning *out) {
             if ((r = ensure_factors(b->slots[sl], st)) != WS_OK) return r;
         total = 0.f;
         for (int k = 0; k < 4; ++k) {
-            hipLaunchKernelGGL(kb_reduce, dim3(b->total[1]), dim3(NTB), 0, st, b->d_desc, b->d_state, b->d_pre[1], n, 1);
             (void)hipEventRecord(e0, st);
+            reduce();
             hipLaunchKernelGGL(kb_lu2_solve, dim3(b->total[2]), dim3(64), 0, st, b->d_desc, b->d_state, b->d_pre[2], n, 1);
             (void)hipEventRecord(e1, st);
             (void)hipEventSynchronize(e1);

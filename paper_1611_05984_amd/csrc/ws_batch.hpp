@@ -159,6 +159,27 @@ __global__ __launch_bounds__(PNT) void kb_pcr(const BatchDesc *__restrict__ desc
     }
 }
 
+// The wave form of PCR over a batch: one wave per system, as k_pcrw; EPL is
+// the batch's largest (at most 8: systems of up to 512 unknowns).
+template <int EPL>
+__global__ __launch_bounds__(64) void kb_pcrw(const BatchDesc *__restrict__ descs,
+                                              const BatchState *__restrict__ states,
+                                              const int *__restrict__ prefix, int ndom, int p) {
+    const int b = blockIdx.x, dm = find_dom(prefix, ndom, b);
+    const BatchDesc &D = descs[dm];
+    const int v = variant(D, states[dm], p);
+    if (v < 0) return;
+    const SolveArgs *g = D.so + v;
+    const int sys = b - prefix[dm], ny = load_params(&g->d.ny);
+    if (sys < ny) {
+        const int N = load_params(&g->d.nu);
+        pcrw_solve<EPL>(N, load_params(&g->redx) + (size_t)sys * N, load_params(&g->solx) + (size_t)sys * N);
+    } else {
+        const int N = load_params(&g->d.nv);
+        pcrw_solve<EPL>(N, load_params(&g->redy) + (size_t)(sys - ny) * N, load_params(&g->soly) + (size_t)(sys - ny) * N);
+    }
+}
+
 __global__ __launch_bounds__(NTB) void kb_expand(const BatchDesc *__restrict__ descs,
                                                 const BatchState *__restrict__ states,
                                                 const int *__restrict__ prefix, int ndom, int p) {

@@ -304,7 +304,7 @@ def test_tunings_identical_results_and_autotuner(tmp_path):
     B.attach(b)
     B.advance(20)
     tb = B.tune()                                  # leaves the states alone
-    assert tb[0] in (8, 16, 24, 32, 48, 64) and tb[1] in (64, 128, 256) and tb[2] in (0, 1, 2, 3)
+    assert tb[0] in (8, 16, 24, 32, 48, 64) and tb[1] in (64, 128, 256) and tb[2] in (0, 1, 2, 3, 4)
     assert tb[3] in (0, 8, 16, 24, 32, 48, 64)
     B.set_tuning(tb[0], tb[1], ws.SOLVE_PCR, tb[3])
     B.advance(20)
@@ -350,8 +350,8 @@ def test_wave_pcr_equals_lds_pcr(nx, ny):
     """PCR on one wave per system (lane shuffles, no LDS array, no barrier)
     gives the bits of the workgroup PCR: reduced systems of 2 x 19 .. 512
     unknowns (every equations-per-lane variant, ragged against the wave),
-    over Euler, predictor and corrector passes.  Longer systems are refused
-    for it, and so is a batch."""
+    over Euler, predictor and corrector passes, alone and in a batch.
+    Longer systems are refused for a single domain."""
     ws = _ws()
     w = wl.config2(nx=nx, ny=ny, seed=13)
     say("case: wave PCR vs workgroup PCR on %s" % w.name)
@@ -367,10 +367,16 @@ def test_wave_pcr_equals_lds_pcr(nx, ny):
     with pytest.raises(ws.WaveStepError) as e:
         big.set_tuning(16, 128, ws.SOLVE_PCR_WAVE)
     assert e.value.status == ws.EINVAL
+    c = make(w)                                     # the same domain in a batch with a small one
+    small = make(wl.config1(nx=70, ny=40))
     B = ws.Batch(2)
-    with pytest.raises(ws.WaveStepError):
-        B.set_tuning(16, 128, ws.SOLVE_PCR_WAVE)
+    B.set_tuning(16, 128, ws.SOLVE_PCR_WAVE)
+    B.attach(c)
+    B.attach(small)
+    B.advance(12)
+    B.sync()
     B.close()
+    same(a, c, "wave PCR in a batch")
 
 
 def test_factored_solve_workgroup_form_and_long_systems():
