@@ -61,7 +61,7 @@ def calib(values, copy_bytes):
 def short(name):
     """Kernel name without return type, namespace and parameter list."""
     n = name[5:] if name.startswith("void ") else name
-    return n.split("(")[0].replace("ws::", "").replace("(anonymous namespace)::", "")
+    return n.replace("(anonymous namespace)::", "").split("(")[0].replace("ws::", "")
 
 
 def source_hash(root):
@@ -130,7 +130,7 @@ def main():
         lines.append("HBM bytes per dispatch (FETCH_SIZE x %.3f, WRITE_SIZE x %.3f; factors from the "
                      "probe copy kernel, %d bytes each way)" % (fs or 0, wsc or 0, a.copy_bytes))
         for name in sorted(fv):
-            head = name.split("(")[0]
+            head = name.replace("(anonymous namespace)::", "").split("(")[0]
             if "ws::" not in head and "k_stream" not in head and "k_copy4" not in head:
                 continue
             rd = [v * fs for v in fv[name]][a.skip:]
