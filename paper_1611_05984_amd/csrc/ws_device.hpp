@@ -180,23 +180,36 @@ __device__ __forceinline__ float shl1z(float v) {
 
 struct F3 { float e, n, t; };  // surface, normal and tangential discharge at a face
 
+// Reconstruction constants of the generalized minmod limiter with parameter
+// theta: minmod(theta a, c/2, theta b) = theta minmod(a, c/(2 theta), b) for
+// theta > 0, and the face values take half the slope, so the limiter runs on
+// the plain differences with the central one scaled by kc = 1/(2 theta), and
+// the face values add or subtract hth = theta/2 times its result (two
+// multiplies fewer a variable).
+struct Recon { float kc, hth; };
+__device__ __forceinline__ Recon recon_k(float th) { return {0.5f / th, 0.5f * th}; }
+
 // Limited linear reconstruction of one cell along one direction, then the
 // conservative positivity correction of the surface against the depths of
 // the cell's low/high faces (w < B  <=>  eta < -D).
 __device__ __forceinline__ void reconstruct(float em, float e0, float ep, float nm, float n0,
                                             float np, float tm, float t0, float tp, float Dlo,
-                                            float Dhi, float th, F3 &lo, F3 &hi) {
-    float se = minmod3(th * (e0 - em), 0.5f * (ep - em), th * (ep - e0));
-    float sn = minmod3(th * (n0 - nm), 0.5f * (np - nm), th * (np - n0));
-    float st = minmod3(th * (t0 - tm), 0.5f * (tp - tm), th * (tp - t0));
-    const float lo_e = e0 - 0.5f * se, hi_e = e0 + 0.5f * se;
+                                            float Dhi, Recon rk, F3 &lo, F3 &hi) {
+    const float me = minmod3(e0 - em, rk.kc * (ep - em), ep - e0);
+    const float mn = minmod3(n0 - nm, rk.kc * (np - nm), np - n0);
+    const float mt = minmod3(t0 - tm, rk.kc * (tp - tm), tp - t0);
+    // explicit fused multiply-adds: theta/2 is not a power of two, so a
+    // multiply and an add would round differently from one fused operation,
+    // and the compiler's choice between the two may differ between kernel
+    // instances (strip heights), which must give the same bits
+    const float lo_e = fmaf(-rk.hth, me, e0), hi_e = fmaf(rk.hth, me, e0);
     const bool fix_hi = hi_e < -Dhi, fix_lo = !fix_hi && lo_e < -Dlo;
     lo.e = fix_hi ? 2.f * e0 + Dhi : (fix_lo ? -Dlo : lo_e);
     hi.e = fix_hi ? -Dhi : (fix_lo ? 2.f * e0 + Dlo : hi_e);
-    lo.n = n0 - 0.5f * sn;
-    hi.n = n0 + 0.5f * sn;
-    lo.t = t0 - 0.5f * st;
-    hi.t = t0 + 0.5f * st;
+    lo.n = fmaf(-rk.hth, mn, n0);
+    hi.n = fmaf(rk.hth, mn, n0);
+    lo.t = fmaf(-rk.hth, mt, t0);
+    hi.t = fmaf(rk.hth, mt, t0);
 }
 
 // Desingularized velocity sqrt(2) h m / sqrt(h^4 + max(h^4, eps)).

@@ -158,7 +158,8 @@ __device__ __forceinline__ void stencil_body(const StencilArgs &A, int bx, int b
     const int col = c0 + lane;
     const int hcol = lane == 0 ? c0 - 1 : c0 + 64;  // halo column held by lanes 0 and 63
     const bool halo_lane = lane == 0 || lane == 63;
-    const float th = d.theta, g = d.g, eps = d.eps;
+    const Recon rk = recon_k(d.theta);
+    const float g = d.g, eps = d.eps;
     const float rdx = d.rdx, rdy = d.rdy, B3 = d.Bd + 1.f / 3.f;
     // strips whose cells and corners (with halo) all lie inside the domain
     // load without boundary handling
@@ -231,7 +232,7 @@ __device__ __forceinline__ void stencil_body(const StencilArgs &A, int bx, int b
         // through its south face (between rows r-2 and r-1)
         const float Dys = 0.5f * (Dl2 + Dr2), Dyn = 0.5f * (Dl3 + Dr3);
         F3 loy, hiy;
-        reconstruct(e2, e3, e4, q1, q2, q3, p1, p2, p3, Dys, Dyn, th, loy, hiy);
+        reconstruct(e2, e3, e4, q1, q2, q3, p1, p2, p3, Dys, Dyn, rk, loy, hiy);
         float Hn0 = 0.f, Hn1 = 0.f, Hn2 = 0.f;  // (mass, y-momentum, x-momentum)
         if (it >= 3) cu_flux(g, eps, Dys, hiy_prev, loy, Hn0, Hn1, Hn2);
 
@@ -266,7 +267,7 @@ __device__ __forceinline__ void stencil_body(const StencilArgs &A, int bx, int b
             const float pm = shr1(p1, hp0), pp = shl1(p1, hp0);
             const float qm = shr1(q1, hq0), qp = shl1(q1, hq0);
             F3 lox, hix;
-            reconstruct(em, e2, ep, pm, p1, pp, qm, q1, qp, Dw, De, th, lox, hix);
+            reconstruct(em, e2, ep, pm, p1, pp, qm, q1, qp, Dw, De, rk, lox, hix);
             const F3 hil = {shr1z(hix.e), shr1z(hix.n), shr1z(hix.t)};
             float Hw0, Hw1, Hw2;  // west face: (mass, x-momentum, y-momentum)
             cu_flux(g, eps, Dw, hil, lox, Hw0, Hw1, Hw2);
