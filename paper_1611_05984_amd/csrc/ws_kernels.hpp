@@ -1301,7 +1301,9 @@ __device__ __forceinline__ void expand_body(const SolveArgs &A, SolveTile &s, in
                                   (s.cz[cy + 2][cx + 1] + s.cz[cy + 2][cx + 2]));
         const float h = e + Dc, h2 = h * h, h4 = h2 * h2;
         if (h4 < d.eps) {  // shoreline: discharge = h * desingularized velocity
-            const float f = 1.41421356237f * h2 * frsq(h4 + d.eps);
+            // h^4 + eps rounded once (an explicit fused multiply-add, so that
+            // every kernel this body is compiled into rounds it alike)
+            const float f = 1.41421356237f * h2 * frsq(fmaf(h2, h2, d.eps));
             P *= f;
             Q *= f;
         }
