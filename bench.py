@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 SOLVERS = ("pcr", "thomas", "lu", "lu2", "pcr_wave")
 # fused-ideal compulsory bytes per cell of one pass: predictor 22 words, corrector 21
-SURVEY_PRED_B, SURVEY_CORR_B = 88.0, 84.0
+FUSED_PRED_B, FUSED_CORR_B = 88.0, 84.0
 # non-packed FP32 VALU issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (lane-instructions/s);
 # packed FP32 instructions are disabled in this build
 VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
@@ -370,7 +370,7 @@ def main():
     kernel_ms_step = tot / args.steps
     step_words = (ALG_WORDS["k_stencil[predictor]"] + 2 * ALG_WORDS["k_stencil[corrector]"] +
                   3 * (ALG_WORDS["k_reduce"] + ALG_WORDS["reduced_solve"] + ALG_WORDS["k_expand"]))
-    survey_b = SURVEY_PRED_B + 2 * SURVEY_CORR_B
+    fused_b = FUSED_PRED_B + 2 * FUSED_CORR_B
     # counter figures of the dominant kernel from the committed profile, used
     # only while the kernel sources are those the counters were taken on
     traffic, valu = None, None
@@ -409,9 +409,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": dom_name, "kernel_ms_avg": kernels[dom]["ms_avg"], "valu": valu,
                      "alg_bytes_per_launch": alg_bytes, "alg_bytes_per_cell": ALG_WORDS[dom] * 4,
-                     "step": {"alg_bytes_per_cell_fused_ideal": survey_b,
-                              "achieved_GBs": value * survey_b / 1e9,
-                              "frac": value * survey_b / 1e9 / HBM_PEAK_GBS,
+                     "step": {"alg_bytes_per_cell_fused_ideal": fused_b,
+                              "achieved_GBs": value * fused_b / 1e9,
+                              "frac": value * fused_b / 1e9 / HBM_PEAK_GBS,
                               "alg_bytes_per_cell_this_design": step_words * 4,
                               "achieved_GBs_this_design": value * step_words * 4 / 1e9,
                               "frac_this_design": value * step_words * 4 / 1e9 / HBM_PEAK_GBS,
