@@ -297,10 +297,14 @@ __device__ __forceinline__ void stencil_body(const StencilArgs &A, int bx, int b
                 const float gb = A.Bg * dep * dep;
                 F += gb * (dep * (exxx + exyy) + ddx * (2.f * exx + eyy) + ddy * exy);
                 G += gb * (dep * (eyyy + exxy) + ddy * (2.f * eyy + exx) + ddx * exy);
-                const float Px = (pp - pm) * A.hx, Py = (p2 - p0) * A.hy;
-                const float Pxy = (shl1z(p2) - shl1z(p0) - shr1z(p2) + shr1z(p0)) * A.cxy;
-                const float Qx = (qp - qm) * A.hx, Qy = (q2 - q0) * A.hy;
-                const float Qxy = (shl1z(q2) - shl1z(q0) - shr1z(q2) + shr1z(q0)) * A.cxy;
+                // cross differences ((P(i+1,j+1) - P(i+1,j-1)) - P(i-1,j+1)) + P(i-1,j-1):
+                // the first difference is the east neighbour's column difference,
+                // shifted (the same value, one lane shift fewer)
+                const float dpy = p2 - p0, dqy = q2 - q0;
+                const float Px = (pp - pm) * A.hx, Py = dpy * A.hy;
+                const float Pxy = (shl1z(dpy) - shr1z(p2) + shr1z(p0)) * A.cxy;
+                const float Qx = (qp - qm) * A.hx, Qy = dqy * A.hy;
+                const float Qxy = (shl1z(dqy) - shr1z(q2) + shr1z(q0)) * A.cxy;
                 Fs = dep * (ddx * Qy + ddy * Qx) * (1.f / 6.f) + B3 * dep * dep * Qxy;
                 Gs = dep * (ddy * Px + ddx * Py) * (1.f / 6.f) + B3 * dep * dep * Pxy;
             }
