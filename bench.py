@@ -32,7 +32,7 @@ SOLVERS = ("pcr", "thomas", "lu", "lu2", "pcr_wave")
 # fused-ideal compulsory bytes per cell of one pass: predictor 22 words, corrector 21
 FUSED_PRED_B, FUSED_CORR_B = 88.0, 84.0
 # non-packed FP32 VALU issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (lane-instructions/s);
-# packed FP32 instructions are disabled in this build
+# the library is compiled without packed FP32 instructions
 VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
 TUNING_CACHE = os.path.join(ROOT, "paper_1611_05984_amd", "tuning_cache.txt")
 
