@@ -140,8 +140,9 @@ ws_status ws_domain_destroy(ws_domain *d);
  * hipMalloc: work being captured into a graph elsewhere, tight serving loops,
  * harnesses that forbid allocation).  The same as ws_domain_init, except that
  * the workspace is the library's own static device array of
- * WS_STATIC_WORKSPACE_BYTES (80 MiB: grids up to 1024 x 512 cells, about
- * 6.9e5 cells of any shape), one per GPU, held from the library's first use
+ * WS_STATIC_WORKSPACE_BYTES (80 MiB: grids up to 1024 x 512 or 768 x 768
+ * cells; about 130 bytes a cell of the grid padded to whole 64 x 16 tiles,
+ * as ws_workspace_bytes reports), one per GPU, held from the library's first use
  * on that GPU until the process ends, and that the handle lives in static
  * storage: the call allocates nothing, on the device or on the host.  It
  * uses the array of the device current at the call (`stream` must belong to
